@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused radiation step on one MI355X.
+
+Workload: Minkowski Cartesian 128^3 periodic box, geodesic level 4 (162
+directions), random fluid velocities |v| <= 0.5, lognormal absorption and
+scattering, collimated beam; FP32 intensities with the FP64 quartic and
+bookkeeping.  A step is one pass of the whole hot path: boundary handling,
+reconstruction, spatial and angular fluxes, divergence, primitives, the
+|n_0| mask, the implicit coupling with its quartic, four-momentum
+bookkeeping and the luminosity.  Inputs are resident in HBM before the timed
+region starts.
+
+Prints one JSON line: value = cell-angle updates per second (FP32 path),
+plus the plain-FP64 rate, the roofline of the step kernel and the CPU
+oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CONFIG = "c2"
+
+
+def _upload_initial(prob, dtype, dev):
+    import numpy as np
+    import torch
+    out = torch.empty((prob.n[2], prob.n[1], prob.n[0], prob.nang), dtype=dtype, device=dev)
+    for k in range(0, prob.n[2], 8):
+        kr = (k, min(prob.n[2], k + 8))
+        out[kr[0]:kr[1]] = torch.as_tensor(prob.initial_intensity(np.float64, kr)).to(dev, dtype)
+    return out
+
+
+def _kernel_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2302_04283_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2302_04283_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(bytes_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_step_c2.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_hash") != _kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_path(prob, precision, steps, warmup, dt, dev):
+    import torch
+    from paper_2302_04283_amd import rt
+    g = rt.Grid(prob, precision, dev.index or 0)
+    Ia = _upload_initial(prob, g.real_dtype(), dev)
+    Ib = torch.empty_like(Ia)
+    T = torch.as_tensor(prob.T).to(dev)
+    rho, u, ka, ks = (torch.as_tensor(x).to(dev) for x in
+                      (prob.rho, prob.u_tet, prob.kappa_a, prob.kappa_s))
+    dT0 = torch.zeros(T.shape + (4,), dtype=torch.float64, device=dev)
+    lum = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        g.step(Ia, Ib, T, rho, u, ka, ks, dt, dT0, lum)
+        Ia, Ib = Ib, Ia
+    torch.cuda.synchronize(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        evs[s][0].record()
+        g.step(Ia, Ib, T, rho, u, ka, ks, dt, dT0, lum)
+        evs[s][1].record()
+        Ia, Ib = Ib, Ia
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) * 1e-3 for a, b in evs]
+    st = g.stats()
+    g.close()
+    del Ia, Ib
+    torch.cuda.empty_cache()
+    return wall, per, st
+
+
+def cpu_baseline(seconds):
+    import torch
+    from oracle import step as O
+    from paper_2302_04283_amd import workloads as W
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    m = 16
+    sub = W.make_problem(CONFIG, sub=((56, 56, 56), (m, m, m)))
+    S = O.setup(sub)
+    dt = O.max_dt(S, sub.cfl)
+    rho, u, ka, ks = O.fluid_tensors(sub)
+    I = torch.as_tensor(sub.initial_intensity())
+    T = torch.as_tensor(sub.T)
+    ba = O.beam_angle(S)
+    O.step(I, T, S, rho, u, ka, ks, dt, ba)   # warm-up
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        I, T, _, _ = O.step(I, T, S, rho, u, ka, ks, dt, ba)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    rate = m ** 3 * sub.nang * n / el
+    return {"value": rate, "unit": "cell-angle updates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d steps of a %d^3-cell block of the 128^3 x 162 workload "
+                      "(torch float64 on %d host threads, %.1f s)" % (n, m, cores, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the radiation step is built and timed on a "
+              "single MI355X (see DESIGN.md for how it would shard); --gpus %d is not "
+              "supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2302_04283_amd import rt
+    from paper_2302_04283_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    prob = W.make_problem(CONFIG)
+    probe = rt.Grid(prob, rt.RT_F32)
+    dt = probe.max_dt(prob.cfl)
+    probe.close()
+    ncell = prob.ncell
+    nang = prob.nang
+    K = args.steps
+    print("[bench] workload %s: %d cells x %d directions, dt=%.6g, %d warmup + %d timed steps"
+          % (CONFIG, ncell, nang, dt, args.warmup, K), file=sys.stderr, flush=True)
+
+    wall32, per32, st32 = time_path(prob, rt.RT_F32, K, args.warmup, dt, dev)
+    print("[bench] fp32 done: %.3f ms/step" % (1e3 * wall32 / K), file=sys.stderr, flush=True)
+    value = ncell * nang * K / wall32
+    # algorithmic bytes per launch: read + write one FP32 intensity per
+    # cell-angle, plus per cell rho, u(3), kappa_a, kappa_s (read), T and
+    # dT0(4) (read + write): 48 + 16 + 64 = 128 B
+    bytes_launch = ncell * (nang * 8 + 128)
+    avg = sum(per32) / len(per32)
+    achieved = bytes_launch / avg / 1e9
+    out = {
+        "metric": "cell-angle updates/s (fwd, FP32 intensities + FP64 solve)",
+        "value": value,
+        "unit": "cell-angle updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall32 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Minkowski Cartesian 128^3 periodic, geodesic level 4 "
+                               "(162 directions), random |v|<=0.5, lognormal kappa_a/kappa_s, "
+                               "collimated beam; FP32 intensities + FP64 quartic",
+                   "cells": ncell, "directions": nang, "dt": dt},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _traffic(bytes_launch),
+                     "kernel": "k_step (fused transport + coupling)",
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "avg_launch_s": avg},
+        "no_root_events": st32["no_root"],
+    }
+    if not args.no_fp64:
+        wall64, per64, _ = time_path(prob, rt.RT_F64, K, args.warmup, dt, dev)
+        print("[bench] fp64 done: %.3f ms/step" % (1e3 * wall64 / K), file=sys.stderr, flush=True)
+        v64 = ncell * nang * K / wall64
+        avg64 = sum(per64) / len(per64)
+        b64 = ncell * (nang * 16 + 128)
+        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * wall64 / K,
+                       "achieved_GBs": b64 / avg64 / 1e9, "speedup_fp32_over_fp64": value / v64}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

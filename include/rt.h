@@ -1,0 +1,182 @@
+/*
+ * rt.h -- C ABI of the MI355X finite-solid-angle GR radiation step.
+ *
+ * The library advances the gray, discrete-angle intensity of White et al.
+ * (2023), "An Extension of the Athena++ Code Framework for Radiation-MHD in
+ * General Relativity Using a Finite-Solid-Angle Discretization": the
+ * conserved variable Q = n^0 n_0 I on a geodesic angular grid (Sec. 2.2,
+ * gray integral form), moved by upwind spatial fluxes (Sec. 2.3-2.4) and
+ * angular fluxes between neighbouring solid angles (Sec. 2.2, 2.6), then
+ * coupled implicitly to a gamma-law gas through the fluid-frame quartic
+ * (Sec. 2.5).
+ *
+ * Conventions
+ *   - Every call returns int: RT_OK (0) or a negative RT_E* code.  The
+ *     message of the last failure on the calling thread is rt_last_error().
+ *     No C++ exception or abort crosses the ABI.
+ *   - Argument checks run synchronously before any launch; an invalid call
+ *     launches nothing and changes nothing.
+ *   - Device pointers ("dev") live on the grid's device; host pointers
+ *     ("host") are read before the call returns.  Kernels run asynchronously
+ *     on the caller's HIP stream (hipStream_t passed as void*; NULL = the
+ *     default stream); the caller keeps its buffers alive until that stream
+ *     has finished with them.  A launch failure returns RT_EDEVICE.
+ *   - Only rt_init_grid allocates device memory; rt_free releases it.  The
+ *     library keeps no pointer to caller memory after a call returns.
+ *   - Cells are indexed (k, j, i) with axis 0 (i) fastest.  Per-cell arrays
+ *     are [n2][n1][n0] (vectors: [..][3], [..][4], ...).  Intensities are
+ *     [n2][n1][n0][nang], angle fastest, in the grid's precision (float for
+ *     RT_F32, double for RT_F64), without ghost cells: boundary values are
+ *     produced inside the kernels from the boundary conditions.
+ *   - All thermodynamic and coupling quantities (T, rho, u, kappa, dT0,
+ *     luminosity) are double in both precisions.
+ *   - Units: c = G = 1; a_rad and k_B/(mu m_p) are descriptor fields.
+ */
+#ifndef PAPER_2302_04283_RT_H
+#define PAPER_2302_04283_RT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rt_grid rt_grid; /* opaque: device tables and scratch */
+
+enum { RT_OK = 0, RT_EINVAL = -1, RT_ENOMEM = -2, RT_EDEVICE = -3, RT_EGEOM = -4 };
+enum { RT_F64 = 0, RT_F32 = 1 };             /* intensity path; the solve is always FP64 */
+enum { RT_RECON_DC = 0, RT_RECON_PLM = 1 };  /* Sec. 2.3 spatial reconstruction          */
+enum { RT_BC_PERIODIC = 0, RT_BC_OUTFLOW_VACUUM = 1 };
+
+/*
+ * Problem statement, all host float64, read only during rt_init_grid.
+ *
+ * Geometry follows Sec. 2.1: the metric g_{ab} in coordinates and a
+ * stationary tetrad e^a_{b^} whose time leg is the normal observer,
+ * e^a_{0^} = -alpha g^{0a}.  Spatial derivatives of both (d_0 = 0 for a
+ * stationary spacetime and tetrad) define the Ricci rotation coefficients
+ * (Sec. 2.2) from which the library forms the angular fluxes.
+ *
+ * Geometry arrays are stored with extent 1 along an axis they do not depend
+ * on: geo_extent[a] is 1 or n[a].  A geometry cell index is
+ * (gk*g1 + gj)*g0 + gi with g = geo_extent.  Face family a (faces normal to
+ * axis a) has extents F[a][b] = g[b] for b != a and, along a,
+ * n[a]+1 if g[a] > 1 else 1.
+ *
+ *   vol[g]         cell volume   int sqrt(-g) dx^1 dx^2 dx^3        (Sec. 2.2)
+ *   area[a][f]     face area     int sqrt(-g) dx^b dx^c               (Sec. 2.2)
+ *   gcov_c[g][4][4]      g_{mu nu} at the cell centre
+ *   dgcov_c[g][3][4][4]  d g_{mu nu} / d x^c, c = 1..3
+ *   tet_c[g][4][4]       e^mu_{b^}  (row mu = coordinate index, column b^)
+ *   dtet_c[g][3][4][4]   d e^mu_{b^} / d x^c
+ *   gcov_f[a][f][4][4], tet_f[a][f][4][4]  the same at face centres
+ *   x_faces[a][n[a]+1]   face coordinates (for the time-step rule only)
+ *
+ * beam_mask (optional, [n2][n1][n0], nonzero = beam cell): after each
+ * step the intensity of direction beam_angle in those cells is set to
+ * beam_I (a fixed-intensity source).
+ */
+typedef struct {
+    int32_t n[3];
+    int32_t geo_extent[3];
+    int32_t nlev;              /* geodesic level N >= 1: nang = 10 N^2 + 2 (Sec. 2.6) */
+    int32_t precision;         /* RT_F32 or RT_F64 */
+    int32_t recon;             /* RT_RECON_DC or RT_RECON_PLM */
+    int32_t bc[3][2];          /* per axis, (lower, upper) */
+    int32_t lum_axis, lum_side;/* face whose outgoing energy flux is the luminosity */
+    double n0_crit;            /* |n_0| below which I is zeroed (Sec. 2.4), paper ~0.1 */
+    double a_rad;              /* radiation constant */
+    double gamma_gas;          /* adiabatic index */
+    double kb_mu_mp;           /* k_B / (mu m_p); c_v = kb_mu_mp / (gamma - 1) */
+    const double *x_faces[3];
+    const double *vol;
+    const double *area[3];
+    const double *gcov_c, *dgcov_c, *tet_c, *dtet_c;
+    const double *gcov_f[3], *tet_f[3];
+    const uint8_t *beam_mask;
+    double beam_I;
+    int32_t beam_angle;
+} rt_grid_desc;
+
+/*
+ * Build the angular grid and the geometry tables on `device` (host FP64),
+ * upload them, and allocate the step's scratch.  Fails with RT_EGEOM if the
+ * tetrad is not orthonormal (|g e e - eta| > 1e-10) or its time leg is not
+ * the normal observer; RT_EINVAL on malformed sizes; RT_ENOMEM if device
+ * memory runs out.  *out is NULL on failure.
+ */
+int rt_init_grid(const rt_grid_desc *desc, int device, rt_grid **out);
+
+/*
+ * Host-only: the geodesic directions of level nlev in canonical order (the
+ * same table rt_angles returns for a grid of that level), nhat[nang][3] and
+ * domega[nang], nang = 10 nlev^2 + 2.  Lets a caller choose directions
+ * (e.g. a beam's) before building a grid.
+ */
+int rt_geodesic_angles(int32_t nlev, double *nhat, double *domega);
+
+/* Number of directions and of angular-grid edges. */
+int rt_grid_info(const rt_grid *g, int32_t *nang, int32_t *nedge);
+
+/*
+ * The angular grid in its canonical order (rings of equal polar angle from
+ * the +x^3 pole, each ring by azimuth from -0.01 rad): unit directions
+ * nhat[nang][3] and solid angles domega[nang] (host, caller-allocated).
+ */
+int rt_angles(const rt_grid *g, double *nhat, double *domega);
+
+/*
+ * Largest stable step for Courant number cfl:
+ *   dt = cfl * min_{cells, dirs} min( min_a dx^a n^0/|n^a|,
+ *                                     dOmega n^0 / sum_{outflow edges} |v| ).
+ * (The paper gives no rule; this per-direction Courant limit is ours.)
+ */
+int rt_max_dt(const rt_grid *g, double cfl, double *dt);
+
+/*
+ * One step (Sec. 2 task order: fluxes -> flux divergence -> primitives ->
+ * implicit coupling), out of place:
+ *   I_in  (dev, const)  intensities at the start of the step
+ *   I_out (dev)         intensities after the step (must not alias I_in)
+ *   T     (dev, in/out) gas temperature [cells]
+ *   rho, kappa_a, kappa_s (dev) [cells]; u_tet (dev) tetrad-frame u^{a^} [cells][3]
+ *   dt    coordinate time step (> 0)
+ *   dT0   (dev, optional) [cells][4], += the change of T^0_alpha that
+ *         balances the radiation four-momentum exchanged by the coupling
+ *         (Sec. 2.5, last paragraph); NULL to skip
+ *   lum   (dev, optional) one double, += dt * (energy per unit time leaving
+ *         through the luminosity face); NULL to skip
+ * Directions with |n_0| < n0_crit leave the step with zero intensity.
+ */
+int rt_step(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
+            const double *rho, const double *u_tet, const double *kappa_a,
+            const double *kappa_s, double dt, double *dT0, double *lum);
+
+/*
+ * Radiation moments per cell (Sec. 2.5):
+ *   R_tet  [cells][10]  R^{a^ b^} = sum_n I n^{a^} n^{b^} dOmega, pairs
+ *                       00 01 02 03 11 12 13 22 23 33 (tetrad frame)
+ *   R0_cov [cells][4]   R^0_alpha = sum_n n^0 n_alpha I dOmega (coordinate)
+ *   E_fluid [cells]     fluid-frame energy density sum_n I (n^0bar)^2 dOmega
+ * Any output may be NULL.  All dev.
+ */
+int rt_moments(rt_grid *g, void *stream, const void *I, const double *u_tet,
+               double *R_tet, double *R0_cov, double *E_fluid);
+
+/*
+ * Running totals since rt_init_grid (synchronises the grid's device):
+ * number of cells whose quartic had no positive root (T set to 1e-12), and
+ * the energy removed by the |n_0| mask.
+ */
+int rt_stats(rt_grid *g, int64_t *no_root_events, double *masked_energy);
+
+/* Release every device table and scratch buffer of g (NULL is a no-op). */
+void rt_free(rt_grid *g);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *rt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

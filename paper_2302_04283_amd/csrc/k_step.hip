@@ -1,0 +1,441 @@
+// Fused radiation step for gfx950 (paper Sec. 2): transport (Sec. 2.3-2.4,
+// 2.6) and implicit coupling (Sec. 2.5) in one pass over the intensities.
+//
+// Mapping: one 64-lane wavefront owns one spatial cell at a time; lane l
+// handles directions l, l+64, ... (NCH chunks).  The coupling's per-cell
+// angle sums are FP64 wavefront reductions, so all directions of a cell stay
+// in one wave and no cross-workgroup traffic is needed.  Boundary values are
+// produced from the boundary conditions inside the kernel (no ghost cells in
+// memory).  Per-block partial sums (luminosity, masked energy, quartic
+// failures) are reduced by a single-block finaliser in a fixed order, so
+// results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "rt_internal.h"
+
+namespace rt {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kCellsPerBlock = 16;
+constexpr double kFourPi = 12.566370614359172953850573533118;
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
+__device__ __forceinline__ int wave_sum_i(int x) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real van_leer(Real dm, Real dp) {
+    Real prod = dm * dp;
+    return prod > Real(0) ? Real(2) * prod / (dm + dp) : Real(0);
+}
+
+// Positive root of B4 T^4 + B1 T + B0 (Sec. 2.5) by Newton's method started
+// at T_hi = min(-B0/B1, (-B0/B4)^(1/4)) >= root: the polynomial is
+// increasing and convex on T >= 0, so the iterates decrease monotonically to
+// the root; stop when they no longer decrease.
+__device__ double quartic_root(double B4, double B1, double B0, int &bad) {
+    bad = 0;
+    if (!(isfinite(B4) && isfinite(B1) && isfinite(B0)) || !(B0 < 0.0) || !(B1 > 0.0)) {
+        bad = 1;
+        return 1e-12;
+    }
+    const double lin = -B0 / B1;
+    if (!(B4 > 0.0)) return lin;
+    double T = fmin(lin, sqrt(sqrt(-B0 / B4)));
+    for (int it = 0; it < 200; ++it) {
+        const double T3 = T * T * T;
+        const double p = B4 * T3 * T + B1 * T + B0;
+        const double dp = 4.0 * B4 * T3 + B1;
+        const double Tn = T - p / dp;
+        if (!(Tn < T)) break;
+        T = Tn;
+    }
+    return T;
+}
+
+struct Cell {
+    int i, j, k;     // cell coordinates
+    long long c;     // linear cell index
+    int gc;          // geometry cell index
+};
+
+__device__ __forceinline__ int face_geo(const DevGrid &G, int a, int fidx, const Cell &x) {
+    const int xi = (a == 0) ? (G.fe[a][0] > 1 ? fidx : 0) : (G.g0 > 1 ? x.i : 0);
+    const int xj = (a == 1) ? (G.fe[a][1] > 1 ? fidx : 0) : (G.g1 > 1 ? x.j : 0);
+    const int xk = (a == 2) ? (G.fe[a][2] > 1 ? fidx : 0) : (G.g2 > 1 ? x.k : 0);
+    return (xk * G.fe[a][1] + xj) * G.fe[a][0] + xi;
+}
+
+// Intensity of direction n in the cell `o` steps along axis a from x, with
+// boundary conditions applied: periodic wrap, or (outflow/vacuum) a copy of
+// the adjacent active cell for directions leaving the domain through that
+// boundary face and zero for directions entering it.
+template <typename Real>
+__device__ __forceinline__ Real nbr(const DevGrid &G, const Real *__restrict__ I, const Cell &x,
+                                    int a, int o, int n) {
+    const int coord = a == 0 ? x.i : (a == 1 ? x.j : x.k);
+    const int len = a == 0 ? G.n0 : (a == 1 ? G.n1 : G.n2);
+    const long long stride = a == 0 ? 1LL : (a == 1 ? (long long)G.n0 : (long long)G.n0 * G.n1);
+    int idx = coord + o;
+    if (idx >= 0 && idx < len) return I[(x.c + (long long)o * stride) * G.nang + n];
+    const int side = idx < 0 ? 0 : 1;
+    if (G.bc[a][side] == RT_BC_PERIODIC) {
+        const int w = ((idx % len) + len) % len;
+        return I[(x.c + (long long)(w - coord) * stride) * G.nang + n];
+    }
+    const int fg = face_geo(G, a, side ? len : 0, x);
+    const int s = G.sgn[a][(size_t)fg * G.nang + n];
+    const bool out = side ? (s > 0) : (s < 0);
+    if (!out) return Real(0);
+    const int edge = side ? len - 1 : 0;
+    return I[(x.c + (long long)(edge - coord) * stride) * G.nang + n];
+}
+
+template <typename Real, int NCH>
+__global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restrict__ Iin,
+                                                 Real *__restrict__ Iout, double *__restrict__ T,
+                                                 const double *__restrict__ rho,
+                                                 const double *__restrict__ uvec,
+                                                 const double *__restrict__ kap_a,
+                                                 const double *__restrict__ kap_s, double dt,
+                                                 double *__restrict__ dT0,
+                                                 double *__restrict__ partials,
+                                                 int *__restrict__ nr_partial) {
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const long long ncell = (long long)G.n0 * G.n1 * G.n2;
+    const int N = G.nang;
+    const Real *q = static_cast<const Real *>(G.q);
+    const Real *vw = static_cast<const Real *>(G.vw);
+    const Real *invV = static_cast<const Real *>(G.invV);
+    const Real dtR = Real(dt);
+    double lum_acc = 0.0, me_acc = 0.0;
+    int nr_acc = 0;
+
+    for (int cw = wave; cw < kCellsPerBlock; cw += kWavesPerBlock) {
+        Cell x;
+        x.c = (long long)blockIdx.x * kCellsPerBlock + cw;
+        if (x.c >= ncell) break;
+        x.i = (int)(x.c % G.n0);
+        x.j = (int)((x.c / G.n0) % G.n1);
+        x.k = (int)(x.c / ((long long)G.n0 * G.n1));
+        x.gc = ((G.g2 > 1 ? x.k : 0) * G.g1 + (G.g1 > 1 ? x.j : 0)) * G.g0 + (G.g0 > 1 ? x.i : 0);
+        const Real ivol = invV[x.gc];
+
+        Real Is[NCH];
+        // ---------------------------------------------------------- transport
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = lane + kWave * ch;
+            Is[ch] = Real(0);
+            if (n >= N) continue;
+            const Real Ic = Iin[x.c * N + n];
+            Real dq = Real(0);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int coord = a == 0 ? x.i : (a == 1 ? x.j : x.k);
+                const int len = a == 0 ? G.n0 : (a == 1 ? G.n1 : G.n2);
+                Real v[5];
+                v[2] = Ic;
+                v[1] = nbr(G, Iin, x, a, -1, n);
+                v[3] = nbr(G, Iin, x, a, +1, n);
+                Real dlm = Real(0), dl0 = Real(0), dlp = Real(0);
+                if (G.recon == RT_RECON_PLM) {
+                    v[0] = nbr(G, Iin, x, a, -2, n);
+                    v[4] = nbr(G, Iin, x, a, +2, n);
+                    dlm = van_leer(v[1] - v[0], v[2] - v[1]);
+                    dl0 = van_leer(v[2] - v[1], v[3] - v[2]);
+                    dlp = van_leer(v[3] - v[2], v[4] - v[3]);
+                }
+                const int flo = face_geo(G, a, coord, x);
+                const int fhi = face_geo(G, a, coord + 1, x);
+                const Real *C = static_cast<const Real *>(G.C[a]);
+                const int slo = G.sgn[a][(size_t)flo * N + n];
+                const int shi = G.sgn[a][(size_t)fhi * N + n];
+                const Real ulo = slo > 0 ? v[1] + Real(0.5) * dlm : (slo < 0 ? v[2] - Real(0.5) * dl0 : Real(0));
+                const Real uhi = shi > 0 ? v[2] + Real(0.5) * dl0 : (shi < 0 ? v[3] - Real(0.5) * dlp : Real(0));
+                const Real Flo = C[(size_t)flo * N + n] * ulo;
+                const Real Fhi = C[(size_t)fhi * N + n] * uhi;
+                dq += Fhi - Flo;
+                if (a == G.lum_axis) {
+                    if (G.lum_side == 1 && coord == len - 1) lum_acc -= G.domega[n] * (double)Fhi;
+                    if (G.lum_side == 0 && coord == 0) lum_acc += G.domega[n] * (double)Flo;
+                }
+            }
+            Real div = Real(0);
+            if (G.has_edges) {
+#pragma unroll
+                for (int s = 0; s < kMaxNbr; ++s) {
+                    const int e = G.adj_e[n * kMaxNbr + s];
+                    if (e < 0) break;
+                    const size_t vi = ((size_t)x.gc * G.nedge + e) * 2;
+                    const Real vv = vw[vi], ww = vw[vi + 1];
+                    const Real up = vv > Real(0) ? Iin[x.c * N + G.edge_lo[e]]
+                                                 : (vv < Real(0) ? Iin[x.c * N + G.edge_hi[e]] : Real(0));
+                    const Real F = ww * up;
+                    div += G.adj_s[n * kMaxNbr + s] > 0 ? F : -F;
+                }
+            }
+            const Real qn = q[(size_t)x.gc * N + n];
+            const Real Qs = qn * Ic - dtR * ivol * dq - dtR * div / Real(G.domega[n]);
+            if (G.mask[(size_t)x.gc * N + n]) {
+                me_acc -= G.volD[x.gc] * G.domega[n] * (double)Qs;
+                Is[ch] = Real(0);
+            } else {
+                Is[ch] = Qs / qn;
+            }
+        }
+
+        // ---------------------------------------------------------- coupling
+        const double u1 = uvec[3 * x.c], u2 = uvec[3 * x.c + 1], u3 = uvec[3 * x.c + 2];
+        const double u0 = sqrt(1.0 + u1 * u1 + u2 * u2 + u3 * u3);
+        const double rh = rho[x.c];
+        const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh, aE = aa + as;
+        const double n0 = G.n0u[x.gc];
+        double Em = 0.0, A1 = 0.0, A2 = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = lane + kWave * ch;
+            if (n >= N || G.mask[(size_t)x.gc * N + n]) continue;
+            const double nb = u0 - (u1 * G.nhat[3 * n] + u2 * G.nhat[3 * n + 1] + u3 * G.nhat[3 * n + 2]);
+            const double dn = n0 + nb * aE * dt;
+            const double w2 = nb * nb * G.domega[n];
+            const double I = (double)Is[ch];
+            Em += I * w2;
+            A1 += (n0 / dn) * I * w2;
+            A2 += G.domega[n] / (nb * dn);
+        }
+        Em = wave_sum(Em);
+        A1 = wave_sum(A1);
+        A2 = wave_sum(A2) * (dt / kFourPi);
+        const double Tm = T[x.c];
+        const double B4 = A2 * aa * G.a_rad;
+        const double B1 = rh * G.cv * (1.0 - A2 * as);
+        const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
+        int bad = 0;
+        const double Tp = quartic_root(B4, B1, B0, bad);
+        const double Ep = Em - rh * G.cv * (Tp - Tm);
+        const double Tp2 = Tp * Tp;
+        const double S = aa * G.a_rad * Tp2 * Tp2 + as * Ep;
+        double M0 = 0.0, M1 = 0.0, M2 = 0.0, M3 = 0.0;
+        const bool beam_cell = G.beam != nullptr && G.beam[x.c];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = lane + kWave * ch;
+            if (n >= N) continue;
+            Real out = Real(0);
+            if (!G.mask[(size_t)x.gc * N + n]) {
+                const double nx = G.nhat[3 * n], ny = G.nhat[3 * n + 1], nz = G.nhat[3 * n + 2];
+                const double nb = u0 - (u1 * nx + u2 * ny + u3 * nz);
+                const double dn = n0 + nb * aE * dt;
+                const double I = (double)Is[ch];
+                const double Ip = (n0 / dn) * I + dt * S / (kFourPi * dn * nb * nb * nb);
+                const double dI = (Ip - I) * G.domega[n];
+                M0 += dI;
+                M1 += dI * nx;
+                M2 += dI * ny;
+                M3 += dI * nz;
+                out = Real(Ip);
+            }
+            if (beam_cell && n == G.beam_angle) out = Real(G.beam_I);
+            Iout[x.c * N + n] = out;
+        }
+        M0 = wave_sum(M0);
+        M1 = wave_sum(M1);
+        M2 = wave_sum(M2);
+        M3 = wave_sum(M3);
+        if (lane == 0) {
+            T[x.c] = Tp;
+            nr_acc += bad;
+            if (dT0) {
+                const double *E0 = G.E0 + 16 * x.gc;
+#pragma unroll
+                for (int al = 0; al < 4; ++al)
+                    dT0[4 * x.c + al] -= n0 * (E0[4 * al] * M0 + E0[4 * al + 1] * M1 +
+                                               E0[4 * al + 2] * M2 + E0[4 * al + 3] * M3);
+            }
+        }
+    }
+    // -------------------------------------------------------- block partials
+    __shared__ double sh_l[kWavesPerBlock], sh_m[kWavesPerBlock];
+    __shared__ int sh_n[kWavesPerBlock];
+    lum_acc = wave_sum(lum_acc);
+    me_acc = wave_sum(me_acc);
+    nr_acc = wave_sum_i(nr_acc);
+    if (lane == 0) {
+        sh_l[wave] = lum_acc;
+        sh_m[wave] = me_acc;
+        sh_n[wave] = nr_acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double l = 0.0, m = 0.0;
+        int r = 0;
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+            l += sh_l[w];
+            m += sh_m[w];
+            r += sh_n[w];
+        }
+        partials[2 * blockIdx.x] = l;
+        partials[2 * blockIdx.x + 1] = m;
+        nr_partial[blockIdx.x] = r;
+    }
+}
+
+// Single-block, fixed-order reduction of the per-block partials.
+__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partials,
+                                                     const int *__restrict__ nr_partial,
+                                                     int nblocks, double dt, double *lum,
+                                                     double *ledger, long long *noroot) {
+    __shared__ double sl[kBlock], sm[kBlock];
+    __shared__ long long sn[kBlock];
+    double l = 0.0, m = 0.0;
+    long long r = 0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+        l += partials[2 * b];
+        m += partials[2 * b + 1];
+        r += nr_partial[b];
+    }
+    sl[threadIdx.x] = l;
+    sm[threadIdx.x] = m;
+    sn[threadIdx.x] = r;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sl[threadIdx.x] += sl[threadIdx.x + s];
+            sm[threadIdx.x] += sm[threadIdx.x + s];
+            sn[threadIdx.x] += sn[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (lum) *lum += dt * sl[0];
+        *ledger += sm[0];
+        *noroot += sn[0];
+    }
+}
+
+// Per-cell moments: one wave per cell, FP64 sums over directions.
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void k_moments(DevGrid G, const Real *__restrict__ I,
+                                                    const double *__restrict__ uvec,
+                                                    double *__restrict__ R,
+                                                    double *__restrict__ R0,
+                                                    double *__restrict__ E) {
+    const int lane = threadIdx.x % kWave;
+    const long long ncell = (long long)G.n0 * G.n1 * G.n2;
+    const long long c = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (c >= ncell) return;
+    const int N = G.nang;
+    double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int n = lane; n < N; n += kWave) {
+        const double w = (double)I[c * N + n] * G.domega[n];
+        const double x = G.nhat[3 * n], y = G.nhat[3 * n + 1], z = G.nhat[3 * n + 2];
+        s[0] += w;
+        s[1] += w * x;
+        s[2] += w * y;
+        s[3] += w * z;
+        s[4] += w * x * x;
+        s[5] += w * x * y;
+        s[6] += w * x * z;
+        s[7] += w * y * y;
+        s[8] += w * y * z;
+        s[9] += w * z * z;
+    }
+#pragma unroll
+    for (int m = 0; m < 10; ++m) s[m] = wave_sum(s[m]);
+    if (lane != 0) return;
+    if (R)
+        for (int m = 0; m < 10; ++m) R[10 * c + m] = s[m];
+    const int i = (int)(c % G.n0), j = (int)((c / G.n0) % G.n1), k = (int)(c / ((long long)G.n0 * G.n1));
+    const int gc = ((G.g2 > 1 ? k : 0) * G.g1 + (G.g1 > 1 ? j : 0)) * G.g0 + (G.g0 > 1 ? i : 0);
+    if (R0) {
+        const double *E0 = G.E0 + 16 * gc;
+        const double n0 = G.n0u[gc];
+        for (int al = 0; al < 4; ++al)
+            R0[4 * c + al] = n0 * (E0[4 * al] * s[0] + E0[4 * al + 1] * s[1] + E0[4 * al + 2] * s[2] +
+                                   E0[4 * al + 3] * s[3]);
+    }
+    if (E) {
+        const double u1 = uvec[3 * c], u2 = uvec[3 * c + 1], u3 = uvec[3 * c + 2];
+        const double u0 = sqrt(1.0 + u1 * u1 + u2 * u2 + u3 * u3);
+        // sum I (u0 - u.n)^2 dOmega from the ten moments
+        E[c] = u0 * u0 * s[0] - 2.0 * u0 * (u1 * s[1] + u2 * s[2] + u3 * s[3]) +
+               u1 * u1 * s[4] + 2.0 * u1 * u2 * s[5] + 2.0 * u1 * u3 * s[6] + u2 * u2 * s[7] +
+               2.0 * u2 * u3 * s[8] + u3 * u3 * s[9];
+    }
+}
+
+template <typename Real>
+int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                  const double *rho, const double *u, const double *ka, const double *ks,
+                  double dt, double *dT0, double *lum) {
+    const DevGrid &G = g->dg;
+    const int nblk = step_blocks(g);
+    const int nch = (G.nang + kWave - 1) / kWave;
+    const Real *in = static_cast<const Real *>(Iin);
+    Real *out = static_cast<Real *>(Iout);
+#define RT_LAUNCH(NC)                                                                          \
+    case NC:                                                                                   \
+        hipLaunchKernelGGL((k_step<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in, out, T, \
+                           rho, u, ka, ks, dt, dT0, g->partials, g->noroot_partial);          \
+        break;
+    switch (nch) {
+        RT_LAUNCH(1)
+        RT_LAUNCH(2)
+        RT_LAUNCH(3)
+        RT_LAUNCH(4)
+        RT_LAUNCH(5)
+        RT_LAUNCH(6)
+        RT_LAUNCH(7)
+        RT_LAUNCH(8)
+        default:
+            return RT_EINVAL;
+    }
+#undef RT_LAUNCH
+    if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, g->partials, g->noroot_partial,
+                       nblk, dt, lum, g->ledger, g->noroot);
+    if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
+    return RT_OK;
+}
+
+}  // namespace
+
+int step_blocks(const rt_grid *g) {
+    const long long ncell = (long long)g->dg.n0 * g->dg.n1 * g->dg.n2;
+    return (int)((ncell + kCellsPerBlock - 1) / kCellsPerBlock);
+}
+
+int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                const double *rho, const double *u, const double *ka, const double *ks,
+                double dt, double *dT0, double *lum) {
+    if (g->precision == RT_F32)
+        return launch_step_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+    return launch_step_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+}
+
+int launch_moments(rt_grid *g, hipStream_t s, const void *I, const double *u, double *R,
+                   double *R0, double *E) {
+    const long long ncell = (long long)g->dg.n0 * g->dg.n1 * g->dg.n2;
+    const int nblk = (int)((ncell + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (g->precision == RT_F32)
+        hipLaunchKernelGGL(k_moments<float>, dim3(nblk), dim3(kBlock), 0, s, g->dg,
+                           static_cast<const float *>(I), u, R, R0, E);
+    else
+        hipLaunchKernelGGL(k_moments<double>, dim3(nblk), dim3(kBlock), 0, s, g->dg,
+                           static_cast<const double *>(I), u, R, R0, E);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
+}
+
+}  // namespace rt

@@ -1,0 +1,357 @@
+// C ABI of the radiation step: validation, table upload, scratch, dispatch.
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <limits>
+#include <new>
+#include <sstream>
+#include <string>
+
+#include "rt_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+struct Uploader {
+    rt_grid *g;
+    int code = RT_OK;
+    std::string msg;
+    template <typename T>
+    T *put(const T *src, size_t count) {
+        if (code != RT_OK) return nullptr;
+        void *p = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            code = RT_ENOMEM;
+            msg = "hipMalloc failed for a geometry table";
+            return nullptr;
+        }
+        g->allocs.push_back(p);
+        if (count && hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+            code = RT_EDEVICE;
+            msg = "hipMemcpy of a geometry table failed";
+            return nullptr;
+        }
+        return static_cast<T *>(p);
+    }
+    template <typename T>
+    T *zeros(size_t count) {
+        if (code != RT_OK) return nullptr;
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+            code = RT_ENOMEM;
+            msg = "hipMalloc failed for scratch";
+            return nullptr;
+        }
+        g->allocs.push_back(p);
+        if (hipMemset(p, 0, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+            code = RT_EDEVICE;
+            msg = "hipMemset of scratch failed";
+        }
+        return static_cast<T *>(p);
+    }
+    // geometry coefficients in the intensity precision
+    const void *real(const std::vector<double> &v, int precision) {
+        if (precision == RT_F64) return put(v.data(), v.size());
+        std::vector<float> f(v.begin(), v.end());
+        return put(f.data(), f.size());
+    }
+};
+
+void release(rt_grid *g) {
+    if (!g) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(g->device);
+    for (void *p : g->allocs) (void)hipFree(p);
+    g->allocs.clear();
+    (void)hipSetDevice(cur);
+}
+
+int check_desc(const rt_grid_desc *d) {
+    if (!d) return fail(RT_EINVAL, "desc is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (d->n[a] < 1) return fail(RT_EINVAL, "n[a] must be >= 1");
+        if (d->geo_extent[a] != 1 && d->geo_extent[a] != d->n[a])
+            return fail(RT_EINVAL, "geo_extent[a] must be 1 or n[a]");
+        for (int s = 0; s < 2; ++s)
+            if (d->bc[a][s] != RT_BC_PERIODIC && d->bc[a][s] != RT_BC_OUTFLOW_VACUUM)
+                return fail(RT_EINVAL, "unknown boundary condition");
+        if ((d->bc[a][0] == RT_BC_PERIODIC) != (d->bc[a][1] == RT_BC_PERIODIC))
+            return fail(RT_EINVAL, "periodic boundaries must be periodic on both sides");
+        if (!d->x_faces[a] || !d->area[a] || !d->gcov_f[a] || !d->tet_f[a])
+            return fail(RT_EINVAL, "missing face geometry");
+    }
+    if ((long long)d->n[0] * d->n[1] * d->n[2] > (1LL << 31) - 1)
+        return fail(RT_EINVAL, "too many cells");
+    if (d->nlev < 1 || d->nlev > 7) return fail(RT_EINVAL, "nlev must be in 1..7 (nang <= 492)");
+    if (d->precision != RT_F32 && d->precision != RT_F64) return fail(RT_EINVAL, "bad precision");
+    if (d->recon != RT_RECON_DC && d->recon != RT_RECON_PLM) return fail(RT_EINVAL, "bad recon");
+    if (d->lum_axis < 0 || d->lum_axis > 2 || d->lum_side < 0 || d->lum_side > 1)
+        return fail(RT_EINVAL, "bad luminosity face");
+    if (!(d->gamma_gas > 1.0) || !(d->kb_mu_mp > 0.0) || !(d->a_rad >= 0.0) || !(d->n0_crit >= 0.0))
+        return fail(RT_EINVAL, "bad physical constants");
+    if (!d->vol || !d->gcov_c || !d->dgcov_c || !d->tet_c || !d->dtet_c)
+        return fail(RT_EINVAL, "missing cell geometry");
+    const int G = d->geo_extent[0] * d->geo_extent[1] * d->geo_extent[2];
+    for (int c = 0; c < G; ++c)
+        if (!(d->vol[c] > 0.0)) return fail(RT_EGEOM, "cell volumes must be positive");
+    if (d->beam_mask) {
+        if (d->beam_angle < 0 || d->beam_angle >= 10 * d->nlev * d->nlev + 2)
+            return fail(RT_EINVAL, "beam_angle out of range");
+    }
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rt_last_error(void) { return g_err.c_str(); }
+
+int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
+    if (!out) return fail(RT_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_desc(d);
+    if (rc != RT_OK) return rc;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(RT_EDEVICE, "no such HIP device");
+    rt_grid *g = nullptr;
+    try {
+        g = new rt_grid();
+        g->device = device;
+        g->precision = d->precision;
+        g->ang = rt::build_geodesic(d->nlev);
+        rt::HostTables t;
+        std::string err;
+        rc = rt::build_tables(*d, g->ang, t, err);
+        if (rc != RT_OK) {
+            delete g;
+            return fail(rc, err);
+        }
+        const int N = g->ang.nang, E = g->ang.nedge;
+        const int G = t.G;
+        // host copies for rt_max_dt
+        for (int a = 0; a < 3; ++a) {
+            g->dx[a].resize(d->n[a]);
+            for (int i = 0; i < d->n[a]; ++i) g->dx[a][i] = d->x_faces[a][i + 1] - d->x_faces[a][i];
+        }
+        g->host_n0u = t.n0u;
+        g->host_vw = t.vw;
+        g->host_na.assign((size_t)G * N * 3, 0.0);
+        for (int c = 0; c < G; ++c) {
+            const double *e = d->tet_c + 16 * c;
+            for (int n = 0; n < N; ++n) {
+                const double *nh = &g->ang.nhat[3 * n];
+                for (int a = 0; a < 3; ++a)
+                    g->host_na[((size_t)c * N + n) * 3 + a] =
+                        e[4 * (a + 1)] + e[4 * (a + 1) + 1] * nh[0] + e[4 * (a + 1) + 2] * nh[1] +
+                        e[4 * (a + 1) + 3] * nh[2];
+            }
+        }
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (hipSetDevice(device) != hipSuccess) {
+            delete g;
+            return fail(RT_EDEVICE, "hipSetDevice failed");
+        }
+        Uploader up{g};
+        rt::DevGrid &v = g->dg;
+        v.n0 = d->n[0];
+        v.n1 = d->n[1];
+        v.n2 = d->n[2];
+        v.nang = N;
+        v.nedge = E;
+        v.g0 = d->geo_extent[0];
+        v.g1 = d->geo_extent[1];
+        v.g2 = d->geo_extent[2];
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b)
+                v.fe[a][b] = (b == a) ? (d->geo_extent[b] > 1 ? d->n[b] + 1 : 1) : d->geo_extent[b];
+            v.bc[a][0] = d->bc[a][0];
+            v.bc[a][1] = d->bc[a][1];
+        }
+        v.recon = d->recon;
+        v.lum_axis = d->lum_axis;
+        v.lum_side = d->lum_side;
+        v.a_rad = d->a_rad;
+        v.cv = d->kb_mu_mp / (d->gamma_gas - 1.0);
+        v.nhat = up.put(g->ang.nhat.data(), g->ang.nhat.size());
+        v.domega = up.put(g->ang.domega.data(), g->ang.domega.size());
+        v.adj_e = up.put(g->ang.adj_e.data(), g->ang.adj_e.size());
+        v.adj_s = up.put(g->ang.adj_s.data(), g->ang.adj_s.size());
+        v.edge_lo = up.put(g->ang.lo.data(), g->ang.lo.size());
+        v.edge_hi = up.put(g->ang.hi.data(), g->ang.hi.size());
+        v.q = up.real(t.q, d->precision);
+        for (int a = 0; a < 3; ++a) {
+            v.C[a] = up.real(t.C[a], d->precision);
+            v.sgn[a] = up.put(t.sgn[a].data(), t.sgn[a].size());
+        }
+        v.vw = up.real(t.vw, d->precision);
+        std::vector<double> invV(G);
+        for (int c = 0; c < G; ++c) invV[c] = 1.0 / t.vol[c];
+        v.invV = up.real(invV, d->precision);
+        v.mask = up.put(t.mask.data(), t.mask.size());
+        v.n0u = up.put(t.n0u.data(), t.n0u.size());
+        v.E0 = up.put(t.E0.data(), t.E0.size());
+        v.volD = up.put(t.vol.data(), t.vol.size());
+        v.has_edges = t.has_edges ? 1 : 0;
+        const size_t ncell = (size_t)d->n[0] * d->n[1] * d->n[2];
+        if (d->beam_mask) {
+            v.beam = up.put(d->beam_mask, ncell);
+            v.beam_angle = d->beam_angle;
+            v.beam_I = d->beam_I;
+        } else {
+            v.beam = nullptr;
+            v.beam_angle = -1;
+            v.beam_I = 0.0;
+        }
+        g->max_blocks = rt::step_blocks(g);
+        g->partials = up.zeros<double>((size_t)g->max_blocks * 2);
+        g->noroot_partial = up.zeros<int>((size_t)g->max_blocks);
+        g->ledger = up.zeros<double>(1);
+        g->noroot = up.zeros<long long>(1);
+        (void)hipSetDevice(cur);
+        if (up.code != RT_OK) {
+            release(g);
+            delete g;
+            return fail(up.code, up.msg);
+        }
+        *out = g;
+        g_err.clear();
+        return RT_OK;
+    } catch (const std::bad_alloc &) {
+        if (g) {
+            release(g);
+            delete g;
+        }
+        return fail(RT_ENOMEM, "host allocation failed");
+    } catch (const std::exception &ex) {
+        if (g) {
+            release(g);
+            delete g;
+        }
+        return fail(RT_EINVAL, ex.what());
+    }
+}
+
+int rt_geodesic_angles(int32_t nlev, double *nhat, double *domega) {
+    if (nlev < 1 || nlev > 7) return fail(RT_EINVAL, "nlev must be in 1..7");
+    try {
+        rt::Geodesic a = rt::build_geodesic(nlev);
+        if (nhat) std::memcpy(nhat, a.nhat.data(), a.nhat.size() * sizeof(double));
+        if (domega) std::memcpy(domega, a.domega.data(), a.domega.size() * sizeof(double));
+    } catch (const std::exception &ex) {
+        return fail(RT_EINVAL, ex.what());
+    }
+    return RT_OK;
+}
+
+int rt_grid_info(const rt_grid *g, int32_t *nang, int32_t *nedge) {
+    if (!g) return fail(RT_EINVAL, "grid is NULL");
+    if (nang) *nang = g->ang.nang;
+    if (nedge) *nedge = g->ang.nedge;
+    return RT_OK;
+}
+
+int rt_angles(const rt_grid *g, double *nhat, double *domega) {
+    if (!g) return fail(RT_EINVAL, "grid is NULL");
+    if (nhat) std::memcpy(nhat, g->ang.nhat.data(), g->ang.nhat.size() * sizeof(double));
+    if (domega) std::memcpy(domega, g->ang.domega.data(), g->ang.domega.size() * sizeof(double));
+    return RT_OK;
+}
+
+int rt_max_dt(const rt_grid *g, double cfl, double *dt) {
+    if (!g || !dt) return fail(RT_EINVAL, "NULL argument");
+    if (!(cfl > 0.0)) return fail(RT_EINVAL, "cfl must be positive");
+    const rt::DevGrid &v = g->dg;
+    const int N = v.nang, E = v.nedge;
+    double best = std::numeric_limits<double>::infinity();
+    for (int gk = 0; gk < v.g2; ++gk)
+        for (int gj = 0; gj < v.g1; ++gj)
+            for (int gi = 0; gi < v.g0; ++gi) {
+                const int c = (gk * v.g1 + gj) * v.g0 + gi;
+                const double n0 = g->host_n0u[c];
+                const double dxs[3] = {g->dx[0][gi], g->dx[1][gj], g->dx[2][gk]};
+                std::vector<double> out(N, 0.0);
+                for (int e = 0; e < E; ++e) {
+                    double vv = g->host_vw[((size_t)c * E + e) * 2];
+                    if (vv > 0) out[g->ang.lo[e]] += vv;
+                    if (vv < 0) out[g->ang.hi[e]] += -vv;
+                }
+                for (int n = 0; n < N; ++n) {
+                    for (int a = 0; a < 3; ++a) {
+                        double na = std::fabs(g->host_na[((size_t)c * N + n) * 3 + a]);
+                        if (na > 0) best = std::fmin(best, dxs[a] * n0 / na);
+                    }
+                    if (out[n] > 0) best = std::fmin(best, g->ang.domega[n] * n0 / out[n]);
+                }
+            }
+    *dt = cfl * best;
+    return RT_OK;
+}
+
+int rt_step(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
+            const double *rho, const double *u_tet, const double *kappa_a,
+            const double *kappa_s, double dt, double *dT0, double *lum) {
+    if (!g) return fail(RT_EINVAL, "grid is NULL");
+    if (!I_in || !I_out || !T || !rho || !u_tet || !kappa_a || !kappa_s)
+        return fail(RT_EINVAL, "NULL state pointer");
+    if (I_in == I_out) return fail(RT_EINVAL, "I_out must not alias I_in");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RT_EINVAL, "dt must be positive and finite");
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    int rc = rt::launch_step(g, (hipStream_t)stream, I_in, I_out, T, rho, u_tet, kappa_a, kappa_s,
+                             dt, dT0, lum);
+    if (cur != g->device) (void)hipSetDevice(cur);
+    if (rc != RT_OK) return fail(rc, "kernel launch failed");
+    return RT_OK;
+}
+
+int rt_moments(rt_grid *g, void *stream, const void *I, const double *u_tet, double *R_tet,
+               double *R0_cov, double *E_fluid) {
+    if (!g) return fail(RT_EINVAL, "grid is NULL");
+    if (!I || (E_fluid && !u_tet)) return fail(RT_EINVAL, "NULL input pointer");
+    if (!R_tet && !R0_cov && !E_fluid) return RT_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    int rc = rt::launch_moments(g, (hipStream_t)stream, I, u_tet, R_tet, R0_cov, E_fluid);
+    if (cur != g->device) (void)hipSetDevice(cur);
+    if (rc != RT_OK) return fail(rc, "kernel launch failed");
+    return RT_OK;
+}
+
+int rt_stats(rt_grid *g, int64_t *no_root_events, double *masked_energy) {
+    if (!g) return fail(RT_EINVAL, "grid is NULL");
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(g->device);
+    long long nr = 0;
+    double me = 0.0;
+    hipError_t e1 = hipDeviceSynchronize();
+    hipError_t e2 = hipMemcpy(&nr, g->noroot, sizeof(nr), hipMemcpyDeviceToHost);
+    hipError_t e3 = hipMemcpy(&me, g->ledger, sizeof(me), hipMemcpyDeviceToHost);
+    (void)hipSetDevice(cur);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return fail(RT_EDEVICE, "reading statistics failed");
+    if (no_root_events) *no_root_events = nr;
+    if (masked_energy) *masked_energy = me;
+    return RT_OK;
+}
+
+void rt_free(rt_grid *g) {
+    if (!g) return;
+    release(g);
+    delete g;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal declarations of the radiation-step library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rt.h"
+
+namespace rt {
+
+constexpr int kMaxNbr = 6;        // polygon edges per direction (5 or 6)
+constexpr int kWave = 64;         // CDNA wavefront
+constexpr int kMaxChunks = 8;     // directions per lane: nang <= 512
+
+// ---------------------------------------------------------------- host grid
+struct Geodesic {
+    int nlev = 0;
+    int nang = 0;
+    int nedge = 0;
+    std::vector<double> nhat;     // [nang][3]
+    std::vector<double> domega;   // [nang]
+    std::vector<int> lo, hi;      // [nedge]
+    std::vector<double> len;      // [nedge]
+    std::vector<double> mid;      // [nedge][3]
+    std::vector<double> nu;       // [nedge][3]  lo -> hi
+    std::vector<int> adj_e;       // [nang][6] edge index or -1
+    std::vector<int> adj_s;       // [nang][6] +1 if the direction is the edge's lo, -1 if hi
+};
+
+Geodesic build_geodesic(int nlev);
+
+// Derived host tables (FP64), geometry-cell major.
+struct HostTables {
+    int G = 0;                    // geometry cells
+    int F[3] = {0, 0, 0};         // faces per family (geometry layout)
+    std::vector<double> q;        // [G][nang]   n^0 n_0 (cell centre)
+    std::vector<double> C[3];     // [F_a][nang] dA n^a n_0 (face centre)
+    std::vector<int8_t> sgn[3];   // [F_a][nang] sign of n^a at the face
+    std::vector<uint8_t> mask;    // [G][nang]   |n_0| < n0_crit
+    std::vector<double> vw;       // [G][nedge][2] (v, w)
+    std::vector<double> n0u;      // [G]         n^0
+    std::vector<double> E0;       // [G][4][4]   g_{a mu} e^mu_{b^}
+    std::vector<double> vol;      // [G]
+    bool has_edges = false;
+    int masked_count = 0;
+};
+
+int build_tables(const rt_grid_desc &d, const Geodesic &ang, HostTables &t,
+                 std::string &err);
+
+// ---------------------------------------------------------------- device view
+struct DevGrid {
+    int n0, n1, n2, nang, nedge;
+    int g0, g1, g2;
+    int fe[3][3];                 // face-family extents [family][axis]
+    int bc[3][2];
+    int recon;
+    int lum_axis, lum_side;
+    double a_rad, cv;
+    // angle tables
+    const double *nhat;           // [nang][3]
+    const double *domega;         // [nang]
+    const int *adj_e;             // [nang][6]
+    const int *adj_s;             // [nang][6]
+    const int *edge_lo, *edge_hi; // [nedge]
+    // geometry tables in the intensity precision
+    const void *q;                // [G][nang]
+    const void *C[3];             // [F_a][nang]
+    const void *vw;               // [G][nedge][2]
+    const void *invV;             // [G]
+    const int8_t *sgn[3];         // [F_a][nang]
+    const uint8_t *mask;          // [G][nang]
+    const double *n0u;            // [G]
+    const double *E0;             // [G][16]
+    const double *volD;           // [G]
+    int has_edges;
+    const uint8_t *beam;          // [cells] or nullptr
+    int beam_angle;
+    double beam_I;
+};
+
+}  // namespace rt
+
+struct rt_grid {
+    int device = 0;
+    int precision = RT_F64;
+    rt::Geodesic ang;
+    rt::DevGrid dg{};
+    std::vector<double> dx[3];    // coordinate widths (for rt_max_dt)
+    std::vector<double> host_n0u; // [G]
+    std::vector<double> host_na;  // [G][nang][3] n^a at centres (for rt_max_dt)
+    std::vector<double> host_vw;  // [G][nedge][2]
+    std::vector<void *> allocs;   // every device allocation
+    // scratch
+    double *partials = nullptr;   // [max_blocks][2]
+    int *noroot_partial = nullptr;// [max_blocks]
+    double *ledger = nullptr;     // [1] masked energy
+    long long *noroot = nullptr;  // [1]
+    int max_blocks = 0;
+};
+
+// kernel launchers (k_step.hip)
+namespace rt {
+int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                const double *rho, const double *u, const double *ka, const double *ks,
+                double dt, double *dT0, double *lum);
+int launch_moments(rt_grid *g, hipStream_t s, const void *I, const double *u,
+                   double *R, double *R0, double *E);
+int step_blocks(const rt_grid *g);
+}  // namespace rt

@@ -1,0 +1,209 @@
+"""Parity of the HIP step (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances (the design doc derives them):
+  FP64 path: intensities 1e-12, gas temperature 1e-13, bookkeeping and
+             luminosity 1e-12 -- the two sides differ only in summation order.
+  FP32 path: intensities 1e-5 (the stated target); gas temperature within the
+             bound that FP32 storage of the intensities allows.
+Intensity errors are |dI| / (|I_oracle| + 1e-3 max|I_oracle|).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from harness import gpu_run, oracle_run, rel_err
+from oracle import step as O
+from paper_2302_04283_amd import rt
+from paper_2302_04283_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+F64_I, F64_T, F64_AUX = 1e-12, 1e-13, 1e-12
+F32_I, F32_T = 1e-5, 2e-7
+
+
+def _report(tag, **errs):
+    print("[parity] %s %s" % (tag, " ".join("%s=%.3e" % kv for kv in errs.items())), flush=True)
+
+
+def _compare(prob, precision, steps, tol_I, tol_T, tag, dt=None, stats=None):
+    S = O.setup(prob)
+    if dt is None:
+        dt = O.max_dt(S, prob.cfl)
+    Io, To, dTo, Jo, _ = oracle_run(prob, steps, dt, stats=stats)
+    Ig, Tg, dTg, Jg, g = gpu_run(prob, precision, steps, dt)
+    eI = rel_err(Ig, Io)
+    eT = float(np.max(np.abs(Tg - To) / To))
+    edT = float(np.max(np.abs(dTg - dTo)) / max(np.abs(dTo).max(), 1e-300))
+    eJ = abs(Jg - Jo) / max(abs(Jo), 1e-300)
+    _report(tag, e_I=eI, e_T=eT, e_dT0=edT, e_J=eJ)
+    assert eI <= tol_I
+    assert eT <= tol_T
+    return dict(eI=eI, eT=eT, edT=edT, eJ=eJ, grid=g, Io=Io, Ig=Ig)
+
+
+def test_c1_fp64():
+    p = W.make_problem("c1")
+    r = _compare(p, rt.RT_F64, p.nsteps, F64_I, F64_T, "c1 fp64 16^3 x42 10 steps")
+    assert r["edT"] <= F64_AUX
+
+
+def test_c1_fp32():
+    p = W.make_problem("c1")
+    _compare(p, rt.RT_F32, p.nsteps, F32_I, F32_T, "c1 fp32 16^3 x42 10 steps")
+
+
+def test_c1_donor_cell_fp64():
+    p = W.make_problem("c1", recon=W.RECON_DC)
+    _compare(p, rt.RT_F64, 5, F64_I, F64_T, "c1 DC fp64")
+
+
+@pytest.mark.parametrize("shape,nlev", [((13, 7, 5), 1), ((9, 11, 6), 3), ((5, 6, 7), 5),
+                                        ((6, 5, 4), 6), ((4, 5, 3), 7)])
+def test_c2_ragged_shapes_and_angle_counts(shape, nlev):
+    # nang 12, 92, 242, 362, 492: one to eight 64-lane chunks, partial last chunk
+    p = W.make_problem("c2", scale=shape, nlev=nlev)
+    r = _compare(p, rt.RT_F64, 3, F64_I, F64_T, "c2 %s lev%d fp64" % (shape, nlev))
+    assert r["edT"] <= F64_AUX
+
+
+def test_c2_small_fp64_and_fp32_beam_velocity_scattering():
+    p = W.make_problem("c2", scale=(16, 16, 16))
+    assert p.beam_mask.any()
+    r = _compare(p, rt.RT_F64, 6, F64_I, F64_T, "c2 16^3 fp64")
+    assert r["edT"] <= F64_AUX
+    _compare(p, rt.RT_F32, 6, F32_I, F32_T, "c2 16^3 fp32")
+    b = rt.beam_direction(p.nlev)
+    assert b == O.beam_angle(O.setup(p))
+    bm = p.beam_mask
+    assert np.all(r["Ig"][bm][:, b] == p.beam_I)
+
+
+def test_kerr_schild_small_fp64_masks_angular_fluxes_outflow():
+    p = W.make_problem("c3", scale=(16, 12, 8))
+    stats = {}
+    r = _compare(p, rt.RT_F64, 4, F64_I, F64_T, "c3-geom 16x12x8 fp64", stats=stats)
+    assert r["edT"] <= F64_AUX and r["eJ"] <= F64_AUX
+    g = r["grid"]
+    st = g.stats()
+    assert st["no_root"] == 0
+    assert abs(st["masked_energy"] - stats["masked_energy"]) <= 1e-12 * abs(stats["masked_energy"])
+    # masked directions are exactly zero on both sides
+    S = O.setup(p)
+    m = np.broadcast_to(S.mask.numpy(), r["Io"].shape)
+    assert np.all(r["Ig"][m] == 0.0) and np.all(r["Io"][m] == 0.0)
+
+
+def test_kerr_schild_small_fp32():
+    p = W.make_problem("c3", scale=(16, 12, 8))
+    _compare(p, rt.RT_F32, 4, F32_I, F32_T, "c3-geom 16x12x8 fp32")
+
+
+def test_kerr_schild_level6_torus_fp64():
+    p = W.make_problem("c5", scale=(12, 8, 6))
+    _compare(p, rt.RT_F64, 2, F64_I, F64_T, "c5-geom 12x8x6 lev6 fp64")
+
+
+def test_max_dt_matches_oracle():
+    for cfg, sc in (("c1", None), ("c3", (32, 16, 8)), ("c4", (16, 8, 8))):
+        p = W.make_problem(cfg, scale=sc)
+        g = rt.Grid(p, rt.RT_F64)
+        dto = O.max_dt(O.setup(p), 0.3)
+        assert abs(g.max_dt(0.3) - dto) <= 1e-14 * dto
+        g.close()
+
+
+def test_moments_match_oracle():
+    p = W.make_problem("c3", scale=(8, 6, 4))
+    S = O.setup(p)
+    I = p.initial_intensity()
+    R, R0, E = O.moments(torch.as_tensor(I), S, torch.as_tensor(p.u_tet))
+    for prec in (rt.RT_F64, rt.RT_F32):
+        g = rt.Grid(p, prec)
+        dev = torch.device("cuda", 0)
+        Rg, R0g, Eg = g.moments(torch.as_tensor(I).to(dev, g.real_dtype()),
+                                torch.as_tensor(p.u_tet).to(dev))
+        tol = 1e-13 if prec == rt.RT_F64 else 1e-6
+        for a, b in ((Rg, R), (R0g, R0), (Eg, E)):
+            err = float((a.cpu() - b).abs().max() / b.abs().max())
+            assert err <= tol, (prec, err)
+
+
+def test_deterministic_bitwise():
+    p = W.make_problem("c3", scale=(16, 8, 8))
+    dt = O.max_dt(O.setup(p), 0.3)
+    a = gpu_run(p, rt.RT_F32, 3, dt)
+    b = gpu_run(p, rt.RT_F32, 3, dt)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[3] == b[3]
+
+
+def test_invalid_arguments_raise():
+    p = W.make_problem("c1")
+    g = rt.Grid(p, rt.RT_F64)
+    dev = torch.device("cuda", 0)
+    I = torch.zeros((16, 16, 16, g.nang), dtype=torch.float64, device=dev)
+    cell = torch.ones((16, 16, 16), dtype=torch.float64, device=dev)
+    u = torch.zeros((16, 16, 16, 3), dtype=torch.float64, device=dev)
+    with pytest.raises(rt.RtError):
+        g.step(I, I, cell, cell, u, cell, cell, 0.01)          # aliasing
+    with pytest.raises(rt.RtError):
+        g.step(I, I.clone(), cell, cell, u, cell, cell, -1.0)  # dt <= 0
+    with pytest.raises(rt.RtError):
+        g.step(I.float(), I.float(), cell, cell, u, cell, cell, 0.01)  # wrong precision
+
+
+# ------------------------------------------------------------ full-size cases
+def _upload_initial(prob, dtype, dev):
+    out = torch.empty((prob.n[2], prob.n[1], prob.n[0], prob.nang), dtype=dtype, device=dev)
+    step = 8
+    for k in range(0, prob.n[2], step):
+        kr = (k, min(prob.n[2], k + step))
+        out[kr[0]:kr[1]] = torch.as_tensor(prob.initial_intensity(np.float64, kr)).to(dev, dtype)
+    return out
+
+
+def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag):
+    full = W.make_problem(cfg)
+    dt = O.max_dt(O.setup(full), full.cfl)
+    dev = torch.device("cuda", 0)
+    g = rt.Grid(full, precision)
+    Ia = _upload_initial(full, g.real_dtype(), dev)
+    Ib = torch.empty_like(Ia)
+    T = torch.as_tensor(full.T).to(dev)
+    args = [torch.as_tensor(x).to(dev) for x in (full.rho, full.u_tet, full.kappa_a, full.kappa_s)]
+    for _ in range(steps):
+        g.step(Ia, Ib, T, *args, dt)
+        Ia, Ib = Ib, Ia
+    torch.cuda.synchronize()
+    halo = 2 * steps
+    sub = W.make_problem(cfg, sub=(tuple(o - halo for o in origin), tuple(m + 2 * halo for _ in range(3))))
+    Io, To, _, _, _ = oracle_run(sub, steps, dt)
+    N = full.n
+    ii = [(origin[a] + np.arange(m)) % N[a] for a in range(3)]
+    Ig = Ia[np.ix_(ii[2], ii[1], ii[0])].double().cpu().numpy()
+    Tg = T.cpu().numpy()[np.ix_(ii[2], ii[1], ii[0])]
+    sl = slice(halo, halo + m)
+    eI = rel_err(Ig, Io[sl, sl, sl])
+    eT = float(np.max(np.abs(Tg - To[sl, sl, sl]) / To[sl, sl, sl]))
+    _report(tag, e_I=eI, e_T=eT)
+    assert eI <= tol_I and eT <= tol_T
+    g.close()
+
+
+def test_c2_full_size_fp32_subbox():
+    # 128^3 x 162 in the launch configuration the benchmark times; the oracle
+    # checks a 16^3 block that contains beam cells and the periodic seam
+    _full_vs_subbox("c2", rt.RT_F32, 2, (-4, 56, 56), 16, F32_I, F32_T,
+                    "c2 full 128^3 fp32 2 steps, block 16^3")
+
+
+def test_c2_full_size_fp64_subbox():
+    _full_vs_subbox("c2", rt.RT_F64, 2, (60, -6, 3), 12, F64_I, F64_T,
+                    "c2 full 128^3 fp64 2 steps, block 12^3")
+
+
+def test_c3_full_size_fp32_subbox():
+    _full_vs_subbox("c3", rt.RT_F32, 2, (50, 24, -8), 12, F32_I, F32_T,
+                    "c3 full 128x64x128 fp32 2 steps, block 12^3")
