@@ -64,6 +64,9 @@ def time_path(prob, precision, steps, warmup, dt, dev):
     import torch
     from paper_2302_04283_amd import rt
     g = rt.Grid(prob, precision, dev.index or 0)
+    print("[bench] %s path: %s kernel" % ("fp32" if precision == rt.RT_F32 else "fp64",
+                                         "tiled" if g.fast_path else "general"),
+          file=sys.stderr, flush=True)
     Ia = _upload_initial(prob, g.real_dtype(), dev)
     Ib = torch.empty_like(Ia)
     T = torch.as_tensor(prob.T).to(dev)

@@ -115,8 +115,12 @@ int rt_init_grid(const rt_grid_desc *desc, int device, rt_grid **out);
  */
 int rt_geodesic_angles(int32_t nlev, double *nhat, double *domega);
 
-/* Number of directions and of angular-grid edges. */
-int rt_grid_info(const rt_grid *g, int32_t *nang, int32_t *nedge);
+/*
+ * Number of directions and of angular-grid edges, and which step kernel the
+ * grid uses: 1 = the tiled fast path for spatially uniform geometry, 0 = the
+ * general kernel.  Any output may be NULL.
+ */
+int rt_grid_info(const rt_grid *g, int32_t *nang, int32_t *nedge, int32_t *fast_path);
 
 /*
  * The angular grid in its canonical order (rings of equal polar angle from

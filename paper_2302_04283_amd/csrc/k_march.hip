@@ -1,0 +1,514 @@
+// Fused radiation step, fast path for geometry that is uniform in space (every
+// geometry table depends on the direction only, no angular fluxes): e.g. flat
+// spacetime in Cartesian coordinates with a constant tetrad (Sec. 2.2).
+//
+// Work decomposition (gfx950):
+//   * a workgroup owns a 4x4 tile of cells in the (axis 0, axis 1) plane and
+//     marches along axis 2 over a segment of planes;
+//   * each cell of the tile is owned by a group of SW lanes (SW = 16, 32 or
+//     64); lane a of the group handles directions a, a+SW, ... (NC of them),
+//     so the coupling's per-cell FP64 angle sums are SW-lane shuffles and the
+//     quartic runs once per lane group, several cells per wavefront;
+//   * axis-2 neighbours come from a five-plane register queue (each plane is
+//     read from HBM once per segment), axis-0/1 neighbours from an LDS copy of
+//     the current plane with a two-cell cross-shaped halo;
+//   * PLM is evaluated on the upwind side only (a face needs only I_L or I_R);
+//     each face value is computed by the same expression from the same inputs
+//     in both cells that share it, so face fluxes telescope exactly;
+//   * workgroups are dispatched round-robin over the 8 XCDs; the logical tile
+//     order is remapped so that each XCD owns a contiguous band of tiles and
+//     halo rows hit its own L2.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+
+#include "k_common.h"
+
+namespace rt {
+namespace {
+
+constexpr int kT = 4;            // tile edge
+constexpr int kTC = kT * kT;     // interior cells per tile
+constexpr int kHalo = 32;        // cross-shaped halo cells (2 deep)
+constexpr int kPlane = kTC + kHalo;
+
+// bits of the per-direction flag byte
+constexpr unsigned kXP = 1, kXN = 2, kYP = 4, kYN = 8, kZP = 16, kZN = 32, kMasked = 64;
+
+__device__ __forceinline__ int plane_slot(int x, int y) {
+    if (x >= 0 && x < kT && y >= 0 && y < kT) return y * kT + x;
+    if (y >= 0 && y < kT) return kTC + y * 4 + (x < 0 ? x + 2 : x - 2);
+    return kTC + 16 + (y < 0 ? y + 2 : y - 2) * 4 + x;
+}
+
+struct Seg {
+    int tx0, ty0, z0, z1;
+};
+
+#ifndef RT_MARCH_WAVES_PER_EU
+#define RT_MARCH_WAVES_PER_EU 2
+#endif
+
+template <typename Real, int SW, int NC>
+__global__ __launch_bounds__(16 * SW) __attribute__((amdgpu_waves_per_eu(RT_MARCH_WAVES_PER_EU)))
+void k_march(
+    DevGrid G, MarchInfo M, const Real *__restrict__ Iin, Real *__restrict__ Iout,
+    double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
+    const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt,
+    double *__restrict__ dT0, double *__restrict__ partials, int *__restrict__ nr_partial) {
+    constexpr int NT = 16 * SW;
+    constexpr int NW = NT / kWave;
+    constexpr int NP = NC * SW;               // padded direction count
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double sh_l[NW], sh_m[NW];
+    __shared__ int sh_n[NW];
+    __shared__ long long s_hrow[kHalo];
+    __shared__ unsigned s_htest[kHalo];
+    __shared__ double s_fl[kTC][8];           // fluid state of the tile's cells
+
+    const int N = G.nang;
+    // XCD-aware remap: the hardware hands block b to XCD b % 8
+    const int per = gridDim.x / 8;
+    const int logical = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (logical >= M.nwork) {
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = 0.0;
+            partials[2 * blockIdx.x + 1] = 0.0;
+            nr_partial[blockIdx.x] = 0;
+        }
+        return;
+    }
+    Seg sg;
+    {
+        const int tile = logical / M.nseg, seg = logical % M.nseg;
+        sg.tx0 = (tile % M.ntx) * kT;
+        sg.ty0 = (tile / M.ntx) * kT;
+        sg.z0 = seg * M.seglen;
+        sg.z1 = min(G.n2, sg.z0 + M.seglen);
+    }
+
+    // LDS: per-direction tables padded to NP entries with neutral values,
+    // then the current plane (tile + halo)
+    double *s_nh = reinterpret_cast<double *>(smem);          // [3][NP]
+    double *s_dom = s_nh + 3 * NP;                            // [NP] dOmega (0 if masked/pad)
+    double *s_dom_all = s_dom + NP;                           // [NP] dOmega (0 if pad)
+    Real *s_tab = reinterpret_cast<Real *>(s_dom_all + NP);   // [5][NP] q, 1/q, cx, cy, cz (signed)
+    Real *s_pl = s_tab + 5 * NP;                              // [kPlane][P]
+    unsigned char *s_bits = reinterpret_cast<unsigned char *>(s_pl + kPlane * M.pstride);  // [NP]
+    const int P = M.pstride;
+
+    for (int i = threadIdx.x; i < NP; i += NT) {
+        const bool live = i < N;
+        const int j = live ? i : 0;
+        const unsigned b = live ? M.bits[j] : 0u;
+        const bool masked = (b & kMasked) != 0;
+        s_nh[i] = live ? G.nhat[3 * j] : 0.0;
+        s_nh[NP + i] = live ? G.nhat[3 * j + 1] : 0.0;
+        s_nh[2 * NP + i] = live ? G.nhat[3 * j + 2] : 0.0;
+        s_dom_all[i] = live ? G.domega[j] : 0.0;
+        s_dom[i] = (live && !masked) ? G.domega[j] : 0.0;
+        s_tab[i] = live ? static_cast<const Real *>(M.q)[j] : Real(1);
+        s_tab[NP + i] = live ? static_cast<const Real *>(M.iq)[j] : Real(1);
+        s_tab[2 * NP + i] = live ? static_cast<const Real *>(M.cx)[j] : Real(0);
+        s_tab[3 * NP + i] = live ? static_cast<const Real *>(M.cy)[j] : Real(0);
+        s_tab[4 * NP + i] = live ? static_cast<const Real *>(M.cz)[j] : Real(0);
+        s_bits[i] = (unsigned char)b;
+    }
+    // halo sources: row index inside a plane, and the flag bit a direction
+    // must carry for an outflow/vacuum ghost to copy the edge cell
+    if (threadIdx.x < kHalo) {
+        const int h = threadIdx.x;
+        int x, y;
+        if (h < 16) {
+            y = h / 4;
+            const int hx = h % 4;
+            x = hx < 2 ? hx - 2 : hx + 2;
+        } else {
+            const int hy = (h - 16) / 4;
+            x = (h - 16) % 4;
+            y = hy < 2 ? hy - 2 : hy + 2;
+        }
+        int gx = sg.tx0 + x, gy = sg.ty0 + y;
+        unsigned test = 0;
+        if (gx < 0 || gx >= G.n0) {
+            const int side = gx < 0 ? 0 : 1;
+            if (G.bc[0][side] == RT_BC_PERIODIC) {
+                gx = ((gx % G.n0) + G.n0) % G.n0;
+            } else {
+                test = side ? kXP : kXN;
+                gx = side ? G.n0 - 1 : 0;
+            }
+        }
+        if (gy < 0 || gy >= G.n1) {
+            const int side = gy < 0 ? 0 : 1;
+            if (G.bc[1][side] == RT_BC_PERIODIC) {
+                gy = ((gy % G.n1) + G.n1) % G.n1;
+            } else {
+                test = side ? kYP : kYN;
+                gy = side ? G.n1 - 1 : 0;
+            }
+        }
+        s_hrow[h] = (long long)gy * G.n0 + gx;
+        s_htest[h] = test;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x % kWave;
+    const int a = lane % SW;
+    const int cl = threadIdx.x / SW;            // tile cell owned by this lane group
+    const int tx = cl % kT, ty = cl / kT;
+    const int gx = sg.tx0 + tx, gy = sg.ty0 + ty;
+    const long long pcells = (long long)G.n0 * G.n1;
+    const long long row = (long long)gy * G.n0 + gx;
+    const Real dtR = Real(dt);
+    const bool plm = G.recon == RT_RECON_PLM;
+    const double vol = M.vol;
+    const double n0u = G.n0u[0];
+    const double *E0 = G.E0;
+    // LDS element offsets of this cell and its axis-0/1 neighbours (-2,-1,+1,+2)
+    const int o_c = plane_slot(tx, ty) * P;
+    const int ox[4] = {plane_slot(tx - 2, ty) * P, plane_slot(tx - 1, ty) * P,
+                       plane_slot(tx + 1, ty) * P, plane_slot(tx + 2, ty) * P};
+    const int oy[4] = {plane_slot(tx, ty - 2) * P, plane_slot(tx, ty - 1) * P,
+                       plane_slot(tx, ty + 1) * P, plane_slot(tx, ty + 2) * P};
+    // luminosity face weights of this cell (0 unless it touches the face)
+    const int lside = G.lum_side;
+    const bool on_lum_xy = (G.lum_axis == 0 && gx == (lside ? G.n0 - 1 : 0)) ||
+                           (G.lum_axis == 1 && gy == (lside ? G.n1 - 1 : 0));
+
+    // plane pz of a row, with the axis-2 boundary condition; `xytest` is the
+    // axis-0/1 outflow test of a halo row (0: always copy)
+    auto load_row = [&](int pz, long long r, unsigned xytest, Real *dst) {
+        long long zz = pz;
+        unsigned test = xytest;
+        if (pz < 0 || pz >= G.n2) {
+            const int side = pz < 0 ? 0 : 1;
+            if (G.bc[2][side] == RT_BC_PERIODIC) {
+                zz = ((pz % G.n2) + G.n2) % G.n2;
+            } else {
+                test |= side ? kZP : kZN;
+                zz = side ? G.n2 - 1 : 0;
+            }
+        }
+        const Real *src = Iin + (zz * pcells + r) * N;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int n = a + SW * k;
+            const Real v = src[min(n, N - 1)];
+            // ghost of an outflow/vacuum boundary: copy for directions leaving
+            // through it (all bits of `test` set; test = 0 always copies)
+            dst[k] = ((s_bits[n] & test) == test) ? v : Real(0);
+        }
+    };
+    const long long hrow0 = s_hrow[2 * cl], hrow1 = s_hrow[2 * cl + 1];
+    const unsigned htest0 = s_htest[2 * cl], htest1 = s_htest[2 * cl + 1];
+    // one fluid field per lane (a < 7): u1 u2 u3 rho kappa_a kappa_s T
+    auto load_fluid = [&](int z) -> double {
+        const long long c = (long long)z * pcells + row;
+        const int f = a < 7 ? a : 6;
+        return f < 3 ? uvec[3 * c + f]
+                     : (f == 3 ? rho[c] : (f == 4 ? kap_a[c] : (f == 5 ? kap_s[c] : T[c])));
+    };
+
+    Real qz[5][NC], hal[2][NC];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) load_row(sg.z0 - 2 + p, row, 0u, qz[p]);
+    load_row(sg.z0, hrow0, htest0, hal[0]);
+    load_row(sg.z0, hrow1, htest1, hal[1]);
+    double flv = load_fluid(sg.z0);
+
+    double lum_acc = 0.0, me_acc = 0.0;
+    int nr_acc = 0;
+
+    for (int z = sg.z0; z < sg.z1; ++z) {
+        // current plane into LDS: own cell from the queue, two halo cells
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int n = a + SW * k;
+            s_pl[o_c + n] = qz[2][k];
+            s_pl[(kTC + 2 * cl) * P + n] = hal[0][k];
+            s_pl[(kTC + 2 * cl + 1) * P + n] = hal[1][k];
+        }
+        if (a < 7) s_fl[cl][a] = flv;
+        __syncthreads();
+        // prefetch the next plane while this one is computed
+        const bool more = z + 1 < sg.z1;
+        Real qn[NC], hn[2][NC];
+        double fln = flv;
+        if (more) {
+            load_row(z + 3, row, 0u, qn);
+            load_row(z + 1, hrow0, htest0, hn[0]);
+            load_row(z + 1, hrow1, htest1, hn[1]);
+            fln = load_fluid(z + 1);
+        }
+        const bool lum_here = on_lum_xy || (G.lum_axis == 2 && z == (lside ? G.n2 - 1 : 0));
+        const bool lum_wave = __ballot(lum_here) != 0;   // wave-uniform
+
+        // ------------------------------------------------------ transport
+        const long long cidx = (long long)z * pcells + row;
+        Real Is[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int n = a + SW * k;
+            const unsigned bits = s_bits[n];
+            const Real Ic = qz[2][k];
+            // upwind-ordered neighbours; a direction without motion along an
+            // axis has a zero coefficient there, so its branch is irrelevant
+            const bool nx = (bits & kXN) != 0, ny = (bits & kYN) != 0, nz = (bits & kZN) != 0;
+            // all four axis-0/1 neighbours at fixed offsets, then the upwind order
+            const Real xm2 = s_pl[ox[0] + n], xm1 = s_pl[ox[1] + n];
+            const Real xp1 = s_pl[ox[2] + n], xp2 = s_pl[ox[3] + n];
+            const Real ym2 = s_pl[oy[0] + n], ym1 = s_pl[oy[1] + n];
+            const Real yp1 = s_pl[oy[2] + n], yp2 = s_pl[oy[3] + n];
+            const Real x0 = nx ? xp2 : xm2, x1 = nx ? xp1 : xm1, x3 = nx ? xm1 : xp1;
+            const Real y0 = ny ? yp2 : ym2, y1 = ny ? yp1 : ym1, y3 = ny ? ym1 : yp1;
+            const Real z0 = nz ? qz[4][k] : qz[0][k];
+            const Real z1 = nz ? qz[3][k] : qz[1][k];
+            const Real z3 = nz ? qz[1][k] : qz[3][k];
+            Real Iax, Ibx, Iay, Iby, Iaz, Ibz;
+            if (plm) {
+                Iax = x1 + half_slope(x0, x1, Ic);
+                Ibx = Ic + half_slope(x1, Ic, x3);
+                Iay = y1 + half_slope(y0, y1, Ic);
+                Iby = Ic + half_slope(y1, Ic, y3);
+                Iaz = z1 + half_slope(z0, z1, Ic);
+                Ibz = Ic + half_slope(z1, Ic, z3);
+            } else {
+                Iax = x1;
+                Ibx = Ic;
+                Iay = y1;
+                Iby = Ic;
+                Iaz = z1;
+                Ibz = Ic;
+            }
+            // signed coefficients: +-C/dV with the sign of the motion
+            const Real cx = s_tab[2 * NP + n], cy = s_tab[3 * NP + n], cz = s_tab[4 * NP + n];
+            const Real Fax = cx * Iax, Fbx = cx * Ibx;
+            const Real Fay = cy * Iay, Fby = cy * Iby;
+            const Real Faz = cz * Iaz, Fbz = cz * Ibz;
+            const Real dq = ((Fbx - Fax) + (Fby - Fay)) + (Fbz - Faz);
+            const Real Qs = s_tab[n] * Ic - dtR * dq;
+            if constexpr (sizeof(Real) == 4)
+                Is[k] = Qs * s_tab[NP + n];
+            else
+                Is[k] = Qs / s_tab[n];
+            if (M.any_mask) {
+                const bool msk = (bits & kMasked) != 0;
+                me_acc -= msk ? vol * s_dom_all[n] * (double)Qs : 0.0;
+                Is[k] = msk ? Real(0) : Is[k];
+            }
+            if (lum_wave) {
+                // energy leaving through the face.  With the signed
+                // coefficients, the face's flux (dA n^a n_0 I_up)/dV is Fb when
+                // the face is on the outflow side of the cell, -Fa when on the
+                // inflow side; the outward orientation of a lower face adds a
+                // minus sign
+                double F = 0.0;
+                if (G.lum_axis == 0) F = (double)(nx == (lside == 0) ? Fbx : -Fax);
+                else if (G.lum_axis == 1) F = (double)(ny == (lside == 0) ? Fby : -Fay);
+                else F = (double)(nz == (lside == 0) ? Fbz : -Faz);
+                lum_acc -= lum_here ? s_dom_all[n] * vol * F : 0.0;
+            }
+        }
+
+        // ------------------------------------------------------ coupling
+        const double u1 = s_fl[cl][0], u2 = s_fl[cl][1], u3 = s_fl[cl][2];
+        const double rh = s_fl[cl][3], aa = s_fl[cl][4] * rh, as = s_fl[cl][5] * rh;
+        const double Tm = s_fl[cl][6];
+        const double u0 = sqrt(1.0 + u1 * u1 + u2 * u2 + u3 * u3);
+        const double tau = (aa + as) * dt;
+        double Em = 0.0, A1 = 0.0, A2 = 0.0;
+        Real kk[NC], gg[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int n = a + SW * k;
+            const double dom = s_dom[n];
+            const double nb = u0 - (u1 * s_nh[n] + u2 * s_nh[NP + n] + u3 * s_nh[2 * NP + n]);
+            const double dn = n0u + nb * tau;
+            const double r = rcp64(nb * nb * dn);      // 1/(nb^2 dn)
+            const double r1 = nb * r;                  // 1/(nb dn)
+            const double kn = n0u * nb * r1;           // n^0/dn
+            const double Iw = (double)Is[k] * (nb * nb * dom);
+            Em += Iw;
+            A1 += kn * Iw;
+            A2 += dom * r1;
+            kk[k] = Real(kn);
+            gg[k] = Real(nb * dn * r * r);             // 1/(dn nb^3)
+        }
+        Em = group_sum<SW>(Em);
+        A1 = group_sum<SW>(A1);
+        A2 = group_sum<SW>(A2) * (dt / kFourPi);
+        const double B4 = A2 * aa * G.a_rad;
+        const double B1 = rh * G.cv * (1.0 - A2 * as);
+        const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
+        int bad = 0;
+        const double Tp = quartic_root_fast(B4, B1, B0, bad);
+        const double Ep = Em - rh * G.cv * (Tp - Tm);
+        const double Tp2 = Tp * Tp;
+        const double S = aa * G.a_rad * Tp2 * Tp2 + as * Ep;
+        const Real cS = Real(dt * S / kFourPi);
+        const bool beam_cell = G.beam != nullptr && G.beam[cidx];
+        double Mv0 = 0.0, Mv1 = 0.0, Mv2 = 0.0, Mv3 = 0.0;
+        Real *dst = Iout + cidx * N;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int n = a + SW * k;
+            const Real Ip = kk[k] * Is[k] + cS * gg[k];
+            const double dI = (double)(Ip - Is[k]) * s_dom[n];
+            Mv0 += dI;
+            Mv1 += dI * s_nh[n];
+            Mv2 += dI * s_nh[NP + n];
+            Mv3 += dI * s_nh[2 * NP + n];
+            Real out = (s_bits[n] & kMasked) ? Real(0) : Ip;
+            out = (beam_cell && n == G.beam_angle) ? Real(G.beam_I) : out;
+            if (k < NC - 1 || n < N) dst[n] = out;
+        }
+        Mv0 = group_sum<SW>(Mv0);
+        Mv1 = group_sum<SW>(Mv1);
+        Mv2 = group_sum<SW>(Mv2);
+        Mv3 = group_sum<SW>(Mv3);
+        if (a == 0) {
+            T[cidx] = Tp;
+            nr_acc += bad;
+            if (dT0) {
+#pragma unroll
+                for (int al = 0; al < 4; ++al)
+                    dT0[4 * cidx + al] -= n0u * (E0[4 * al] * Mv0 + E0[4 * al + 1] * Mv1 +
+                                                 E0[4 * al + 2] * Mv2 + E0[4 * al + 3] * Mv3);
+            }
+        }
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                qz[0][k] = qz[1][k];
+                qz[1][k] = qz[2][k];
+                qz[2][k] = qz[3][k];
+                qz[3][k] = qz[4][k];
+                qz[4][k] = qn[k];
+                hal[0][k] = hn[0][k];
+                hal[1][k] = hn[1][k];
+            }
+            flv = fln;
+        }
+    }
+
+    // per-block partial sums (fixed order)
+    const int wave = threadIdx.x / kWave;
+    lum_acc = group_sum<kWave>(lum_acc);
+    me_acc = group_sum<kWave>(me_acc);
+    nr_acc = group_sum_i<kWave>(nr_acc);
+    if (lane == 0) {
+        sh_l[wave] = lum_acc;
+        sh_m[wave] = me_acc;
+        sh_n[wave] = nr_acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double l = 0.0, m = 0.0;
+        int r = 0;
+        for (int w = 0; w < NW; ++w) {
+            l += sh_l[w];
+            m += sh_m[w];
+            r += sh_n[w];
+        }
+        partials[2 * blockIdx.x] = l;
+        partials[2 * blockIdx.x + 1] = m;
+        nr_partial[blockIdx.x] = r;
+    }
+}
+
+template <typename Real, int SW, int NC>
+int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+               const double *rho, const double *u, const double *ka, const double *ks,
+               double dt, double *dT0) {
+    const MarchInfo &M = g->march;
+    static bool lds_set = false;   // one attribute call per instantiation
+    if (!lds_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march<Real, SW, NC>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)M.lds) != hipSuccess)
+            return RT_EDEVICE;
+        lds_set = true;
+    }
+    hipLaunchKernelGGL((k_march<Real, SW, NC>), dim3(M.grid), dim3(16 * SW), M.lds, s, g->dg, M,
+                       static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho, u, ka,
+                       ks, dt, dT0, g->partials, g->noroot_partial);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
+}
+
+}  // namespace
+
+// Lane-group width and directions per lane for each supported direction count.
+bool march_config(int precision, int nang, int &sw, int &nc) {
+    // instantiated (lane-group width, directions per lane) pairs
+    static const int f32[][2] = {{16, 1}, {16, 3}, {16, 6}, {16, 11}, {32, 3}, {32, 6},
+                                 {32, 8}, {32, 12}, {64, 3}};
+    static const int f64[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 6}, {64, 3}};
+    int want = 0;
+    if (const char *e = std::getenv("RT_MARCH_SW")) want = std::atoi(e);
+    const int (*tab)[2] = precision == RT_F32 ? f32 : f64;
+    const int ntab = precision == RT_F32 ? 9 : 6;
+    // smallest group width whose directions-per-lane fits the register budget
+    const int budget = precision == RT_F32 ? 6 : 3;
+    for (int w : {16, 32, 64}) {
+        if (want && w != want) continue;
+        const int need = (nang + w - 1) / w;
+        if (!want && need > budget) continue;
+        for (int i = 0; i < ntab; ++i)
+            if (tab[i][0] == w && tab[i][1] == need) {
+                sw = w;
+                nc = need;
+                return true;
+            }
+    }
+    return false;
+}
+
+// LDS stride of one plane cell: the direction count rounded so that the
+// lane groups of a wavefront, which read neighbouring plane cells, start on
+// different LDS banks
+int march_pstride(int precision, int nang) {
+    const int per_bank_row = precision == RT_F32 ? 64 : 32;   // 256-byte rows
+    const int quarter = per_bank_row / 4;
+    int p = (nang + quarter - 1) / quarter * quarter;
+    if ((p / quarter) % 2 == 0) p += quarter;
+    return p;
+}
+
+size_t march_lds_bytes(int precision, int nang, int np) {
+    const size_t real = precision == RT_F32 ? 4 : 8;
+    return (size_t)np * (5 * 8 + 5 * real + 1) +
+           (size_t)kPlane * march_pstride(precision, np) * real;
+}
+
+int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                 const double *rho, const double *u, const double *ka, const double *ks,
+                 double dt, double *dT0) {
+    const MarchInfo &M = g->march;
+#define RT_CASE(R, SW, NC)                                                                    \
+    if (M.sw == SW && M.nc == NC)                                                             \
+        return launch_one<R, SW, NC>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0);
+    if (g->precision == RT_F32) {
+        RT_CASE(float, 16, 1)
+        RT_CASE(float, 16, 3)
+        RT_CASE(float, 16, 6)
+        RT_CASE(float, 16, 11)
+        RT_CASE(float, 32, 3)
+        RT_CASE(float, 32, 6)
+        RT_CASE(float, 32, 8)
+        RT_CASE(float, 32, 12)
+        RT_CASE(float, 64, 3)
+    } else {
+        RT_CASE(double, 16, 1)
+        RT_CASE(double, 16, 3)
+        RT_CASE(double, 16, 6)
+        RT_CASE(double, 32, 3)
+        RT_CASE(double, 32, 6)
+        RT_CASE(double, 64, 3)
+    }
+#undef RT_CASE
+    return RT_EINVAL;
+}
+
+}  // namespace rt

@@ -11,7 +11,7 @@
 // results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
-#include "rt_internal.h"
+#include "k_common.h"
 
 namespace rt {
 namespace {
@@ -19,48 +19,13 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kCellsPerBlock = 16;
-constexpr double kFourPi = 12.566370614359172953850573533118;
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
-    return x;
-}
-
-__device__ __forceinline__ int wave_sum_i(int x) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
-    return x;
-}
+__device__ __forceinline__ double wave_sum(double x) { return group_sum<kWave>(x); }
+__device__ __forceinline__ int wave_sum_i(int x) { return group_sum_i<kWave>(x); }
 
 template <typename Real>
 __device__ __forceinline__ Real van_leer(Real dm, Real dp) {
     Real prod = dm * dp;
     return prod > Real(0) ? Real(2) * prod / (dm + dp) : Real(0);
-}
-
-// Positive root of B4 T^4 + B1 T + B0 (Sec. 2.5) by Newton's method started
-// at T_hi = min(-B0/B1, (-B0/B4)^(1/4)) >= root: the polynomial is
-// increasing and convex on T >= 0, so the iterates decrease monotonically to
-// the root; stop when they no longer decrease.
-__device__ double quartic_root(double B4, double B1, double B0, int &bad) {
-    bad = 0;
-    if (!(isfinite(B4) && isfinite(B1) && isfinite(B0)) || !(B0 < 0.0) || !(B1 > 0.0)) {
-        bad = 1;
-        return 1e-12;
-    }
-    const double lin = -B0 / B1;
-    if (!(B4 > 0.0)) return lin;
-    double T = fmin(lin, sqrt(sqrt(-B0 / B4)));
-    for (int it = 0; it < 200; ++it) {
-        const double T3 = T * T * T;
-        const double p = B4 * T3 * T + B1 * T + B0;
-        const double dp = 4.0 * B4 * T3 + B1;
-        const double Tn = T - p / dp;
-        if (!(Tn < T)) break;
-        T = Tn;
-    }
-    return T;
 }
 
 struct Cell {
@@ -404,10 +369,7 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
     }
 #undef RT_LAUNCH
     if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, g->partials, g->noroot_partial,
-                       nblk, dt, lum, g->ledger, g->noroot);
-    if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
-    return RT_OK;
+    return launch_finalize(g, s, nblk, dt, lum);
 }
 
 }  // namespace
@@ -417,9 +379,20 @@ int step_blocks(const rt_grid *g) {
     return (int)((ncell + kCellsPerBlock - 1) / kCellsPerBlock);
 }
 
+int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *lum) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, g->partials, g->noroot_partial,
+                       nblocks, dt, lum, g->ledger, g->noroot);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
+}
+
 int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                 const double *rho, const double *u, const double *ka, const double *ks,
                 double dt, double *dT0, double *lum) {
+    if (g->march.enabled) {
+        int rc = launch_march(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0);
+        if (rc != RT_OK) return rc;
+        return launch_finalize(g, s, g->march.grid, dt, lum);
+    }
     if (g->precision == RT_F32)
         return launch_step_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
     return launch_step_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);

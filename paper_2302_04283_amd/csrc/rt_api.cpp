@@ -1,5 +1,7 @@
 // C ABI of the radiation step: validation, table upload, scratch, dispatch.
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <limits>
@@ -213,7 +215,65 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
             v.beam_angle = -1;
             v.beam_I = 0.0;
         }
-        g->max_blocks = rt::step_blocks(g);
+        // fast path for spatially uniform geometry
+        {
+            rt::MarchInfo &M = g->march;
+            M.enabled = 0;
+            M.any_mask = 0;
+            int sw = 0, nc = 0;
+            const char *env = std::getenv("RT_MARCH");
+            const bool allow = !(env && env[0] == '0');
+            const bool cfg = rt::march_config(d->precision, N, sw, nc);
+            const size_t lds = cfg ? rt::march_lds_bytes(d->precision, N, sw * nc) : 0;
+            if (allow && cfg && G == 1 && !t.has_edges && d->n[0] % 4 == 0 && d->n[1] % 4 == 0 &&
+                lds <= 150 * 1024) {
+                std::vector<double> q(N), iq(N), cx(N), cy(N), cz(N);
+                std::vector<uint8_t> bits(N, 0);
+                for (int n = 0; n < N; ++n) {
+                    q[n] = t.q[n];
+                    iq[n] = 1.0 / t.q[n];
+                    // flux coefficients C/dV with the sign of the motion folded in
+                    cx[n] = (t.sgn[0][n] < 0 ? -1.0 : 1.0) * t.C[0][n] * invV[0];
+                    cy[n] = (t.sgn[1][n] < 0 ? -1.0 : 1.0) * t.C[1][n] * invV[0];
+                    cz[n] = (t.sgn[2][n] < 0 ? -1.0 : 1.0) * t.C[2][n] * invV[0];
+                    uint8_t b = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        if (t.sgn[a][n] > 0) b |= (uint8_t)(1u << (2 * a));
+                        if (t.sgn[a][n] < 0) b |= (uint8_t)(2u << (2 * a));
+                    }
+                    if (t.mask[n]) b |= 64;
+                    bits[n] = b;
+                    if (t.mask[n]) M.any_mask = 1;
+                }
+                M.q = up.real(q, d->precision);
+                M.iq = up.real(iq, d->precision);
+                M.cx = up.real(cx, d->precision);
+                M.cy = up.real(cy, d->precision);
+                M.cz = up.real(cz, d->precision);
+                M.bits = up.put(bits.data(), bits.size());
+                M.vol = t.vol[0];
+                M.sw = sw;
+                M.nc = nc;
+                M.lds = lds;
+                M.pstride = rt::march_pstride(d->precision, sw * nc);
+                M.ntx = d->n[0] / 4;
+                const long long ntiles = (long long)(d->n[0] / 4) * (d->n[1] / 4);
+                long long target = 2048;
+                if (const char *w = std::getenv("RT_MARCH_WG")) target = std::max(1LL, std::atoll(w));
+                long long seglen = std::max<long long>(4, (d->n[2] * ntiles + target - 1) / target);
+                if (const char *sl = std::getenv("RT_MARCH_SEGLEN")) seglen = std::max(1LL, std::atoll(sl));
+                seglen = std::min<long long>(seglen, d->n[2]);
+                M.seglen = (int)seglen;
+                M.nseg = (int)((d->n[2] + seglen - 1) / seglen);
+                const long long nwork = ntiles * M.nseg;
+                if (nwork < (1LL << 30)) {
+                    M.nwork = (int)nwork;
+                    M.grid = (int)((nwork + 7) / 8 * 8);
+                    M.enabled = 1;
+                }
+            }
+        }
+        g->max_blocks = std::max(rt::step_blocks(g), g->march.enabled ? g->march.grid : 0);
         g->partials = up.zeros<double>((size_t)g->max_blocks * 2);
         g->noroot_partial = up.zeros<int>((size_t)g->max_blocks);
         g->ledger = up.zeros<double>(1);
@@ -254,10 +314,11 @@ int rt_geodesic_angles(int32_t nlev, double *nhat, double *domega) {
     return RT_OK;
 }
 
-int rt_grid_info(const rt_grid *g, int32_t *nang, int32_t *nedge) {
+int rt_grid_info(const rt_grid *g, int32_t *nang, int32_t *nedge, int32_t *fast_path) {
     if (!g) return fail(RT_EINVAL, "grid is NULL");
     if (nang) *nang = g->ang.nang;
     if (nedge) *nedge = g->ang.nedge;
+    if (fast_path) *fast_path = g->march.enabled;
     return RT_OK;
 }
 

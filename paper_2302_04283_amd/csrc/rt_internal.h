@@ -82,6 +82,19 @@ struct DevGrid {
     double beam_I;
 };
 
+// Fast path for spatially uniform geometry (k_march.hip).
+struct MarchInfo {
+    int enabled;
+    int sw, nc;                   // lane-group width, directions per lane
+    int ntx, nseg, seglen, nwork, grid;
+    int pstride;                  // LDS stride of a plane cell
+    int any_mask;                 // some direction is masked
+    size_t lds;                   // dynamic LDS bytes
+    const void *q, *iq, *cx, *cy, *cz;   // per-direction tables (intensity precision)
+    const uint8_t *bits;          // per-direction sign/mask flags
+    double vol;
+};
+
 }  // namespace rt
 
 struct rt_grid {
@@ -89,6 +102,7 @@ struct rt_grid {
     int precision = RT_F64;
     rt::Geodesic ang;
     rt::DevGrid dg{};
+    rt::MarchInfo march{};
     std::vector<double> dx[3];    // coordinate widths (for rt_max_dt)
     std::vector<double> host_n0u; // [G]
     std::vector<double> host_na;  // [G][nang][3] n^a at centres (for rt_max_dt)
@@ -110,4 +124,11 @@ int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *
 int launch_moments(rt_grid *g, hipStream_t s, const void *I, const double *u,
                    double *R, double *R0, double *E);
 int step_blocks(const rt_grid *g);
+bool march_config(int precision, int nang, int &sw, int &nc);
+size_t march_lds_bytes(int precision, int nang, int np);
+int march_pstride(int precision, int nang);
+int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                 const double *rho, const double *u, const double *ka, const double *ks,
+                 double dt, double *dT0);
+int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *lum);
 }  // namespace rt

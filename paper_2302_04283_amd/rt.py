@@ -70,7 +70,8 @@ def load():
     vp = C.c_void_p
     lib.rt_init_grid.argtypes = [C.POINTER(RtGridDesc), C.c_int, C.POINTER(vp)]
     lib.rt_geodesic_angles.argtypes = [C.c_int32, _dp, _dp]
-    lib.rt_grid_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.rt_grid_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]
     lib.rt_angles.argtypes = [vp, _dp, _dp]
     lib.rt_max_dt.argtypes = [vp, C.c_double, _dp]
     lib.rt_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
@@ -166,10 +167,11 @@ class Grid:
         self.device = device
         self.precision = precision
         self.n = tuple(int(v) for v in prob.n)
-        na, ne = C.c_int32(), C.c_int32()
-        _check(lib.rt_grid_info(h, C.byref(na), C.byref(ne)))
+        na, ne, fp = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib.rt_grid_info(h, C.byref(na), C.byref(ne), C.byref(fp)))
         self.nang = na.value
         self.nedge = ne.value
+        self.fast_path = bool(fp.value)
 
     # -------------------------------------------------------------- queries
     def angles(self):

@@ -169,6 +169,7 @@ def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag):
     dt = O.max_dt(O.setup(full), full.cfl)
     dev = torch.device("cuda", 0)
     g = rt.Grid(full, precision)
+    print("[parity] %s uses the %s kernel" % (tag, "tiled" if g.fast_path else "general"), flush=True)
     Ia = _upload_initial(full, g.real_dtype(), dev)
     Ib = torch.empty_like(Ia)
     T = torch.as_tensor(full.T).to(dev)
@@ -207,3 +208,45 @@ def test_c2_full_size_fp64_subbox():
 def test_c3_full_size_fp32_subbox():
     _full_vs_subbox("c3", rt.RT_F32, 2, (50, 24, -8), 12, F32_I, F32_T,
                     "c3 full 128x64x128 fp32 2 steps, block 12^3")
+
+
+# ------------------------------------------------------------ tiled fast path
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("shape,nlev", [((8, 12, 5), 1), ((4, 4, 9), 2), ((12, 8, 3), 3),
+                                        ((8, 8, 7), 4)])
+def test_fast_path_tiles(shape, nlev, prec):
+    p = W.make_problem("c2", scale=shape, nlev=nlev)
+    g = rt.Grid(p, prec)
+    assert g.fast_path
+    g.close()
+    tol = (F64_I, F64_T) if prec == rt.RT_F64 else (F32_I, F32_T)
+    r = _compare(p, prec, 4, *tol, "fast %s lev%d %s" % (shape, nlev, "fp64" if prec == 0 else "fp32"))
+    if prec == rt.RT_F64:
+        assert r["edT"] <= F64_AUX and r["eJ"] <= F64_AUX
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+def test_fast_path_outflow_vacuum_boundaries(prec):
+    p = W.make_custom("minkowski_cart", (8, 8, 6), [(0.0, 1.0)] * 3, 3,
+                      [(1, 1), (1, 1), (1, 1)])
+    rng = np.random.default_rng(3)
+    p.T[:] = 0.5 + rng.random(p.T.shape)
+    p.kappa_a[:] = 5.0 * rng.random(p.T.shape)
+    p.kappa_s[:] = 5.0 * rng.random(p.T.shape)
+    for ax in range(3):
+        p.lum_axis, p.lum_side = ax, ax % 2
+        g = rt.Grid(p, prec)
+        assert g.fast_path
+        g.close()
+        tol = (F64_I, F64_T) if prec == rt.RT_F64 else (F32_I, F32_T)
+        r = _compare(p, prec, 5, *tol, "fast outflow lum axis %d" % ax)
+        assert r["eJ"] <= (F64_AUX if prec == rt.RT_F64 else 1e-5)
+
+
+def test_general_kernel_forced_matches_oracle(monkeypatch):
+    monkeypatch.setenv("RT_MARCH", "0")
+    p = W.make_problem("c2", scale=(8, 8, 8))
+    g = rt.Grid(p, rt.RT_F64)
+    assert not g.fast_path
+    g.close()
+    _compare(p, rt.RT_F64, 3, F64_I, F64_T, "general kernel forced, 8^3 fp64")
