@@ -96,6 +96,38 @@ def time_path(prob, precision, steps, warmup, dt, dev):
     return wall, per, st
 
 
+def time_fwd_adjoint(prob, precision, steps, ckpt, dt, dev):
+    """Forward with a checkpoint every `ckpt` steps plus the hand-written
+    adjoint (segment recompute + reverse steps): whole-job wall time."""
+    import torch
+    from paper_2302_04283_amd import rt
+    from paper_2302_04283_amd.autograd import RadTransport
+    g = rt.Grid(prob, precision, dev.index or 0)
+    I0 = _upload_initial(prob, g.real_dtype(), dev)
+    T0 = torch.as_tensor(prob.T).to(dev)
+    rho, u, ka, ks = (torch.as_tensor(x).to(dev) for x in
+                      (prob.rho, prob.u_tet, prob.kappa_a, prob.kappa_s))
+
+    def run(n):
+        kk = ka.clone().requires_grad_(True)
+        tt = T0.clone().requires_grad_(True)
+        J = RadTransport.apply(I0, tt, kk, ks, g, rho, u, dt, n, ckpt)
+        J.backward()
+        return kk.grad
+
+    run(2)                                   # warm-up
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    gk = run(steps)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    finite = bool(torch.isfinite(gk).all())
+    g.close()
+    del I0
+    torch.cuda.empty_cache()
+    return wall, finite
+
+
 def cpu_baseline(seconds):
     import torch
     from oracle import step as O
@@ -133,6 +165,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--checkpoint-every", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the radiation step is built and timed on a "
@@ -197,6 +231,16 @@ def main():
         b64 = ncell * (nang * 16 + 128)
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * wall64 / K,
                        "achieved_GBs": b64 / avg64 / 1e9, "speedup_fp32_over_fp64": value / v64}
+    if not args.no_adjoint:
+        wall_fa, finite = time_fwd_adjoint(prob, rt.RT_F32, K, args.checkpoint_every, dt, dev)
+        print("[bench] fwd+adjoint done: %.3f ms/step" % (1e3 * wall_fa / K), file=sys.stderr,
+              flush=True)
+        out["fwd_adjoint"] = {"value": ncell * nang * K / wall_fa, "unit": "cell-angle updates/s",
+                              "ms_per_step": 1e3 * wall_fa / K,
+                              "checkpoint_every": args.checkpoint_every,
+                              "gradients_finite": finite,
+                              "functional": "luminosity through the upper x face; gradients "
+                                            "wrt kappa_a and T0"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)

@@ -157,6 +157,27 @@ int rt_step(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
             const double *kappa_s, double dt, double *dT0, double *lum);
 
 /*
+ * Adjoint of rt_step for the functional J = sum over steps of
+ * w_s * dt * l(I_s), l the luminosity of rt_step.  Given the state at the
+ * start of step s (I_n, T_n, the same fluid, opacities and dt) and
+ * lamI_np1 = dJ/dI_{s+1}, lamT_np1 = dJ/dT_{s+1}, it writes
+ * lamI_n = dJ/dI_s and lamT_n = dJ/dT_s and adds this step's share of
+ * dJ/dkappa_a and dJ/dkappa_s.  lum_weight is w_s (1 for J = sum dt l).
+ * The quartic is reversed with the implicit-function theorem; the PLM
+ * limiter with its Jacobian on the branch the forward step took.
+ *   I_n, lamI_np1, lamI_n, work (dev) [n2][n1][n0][nang], grid precision;
+ *     lamI_n may alias lamI_np1 (read completely before lamI_n is written);
+ *     work is caller-owned scratch of the same size, not aliasing the others
+ *   T_n, lamT_np1, lamT_n (dev) [cells]; lamT_n may alias lamT_np1
+ *   grad_kappa_a, grad_kappa_s (dev) [cells], accumulated (+=), or NULL
+ */
+int rt_step_adjoint(rt_grid *g, void *stream, const void *I_n, const double *T_n,
+                    const double *rho, const double *u_tet, const double *kappa_a,
+                    const double *kappa_s, double dt, double lum_weight, const void *lamI_np1,
+                    const double *lamT_np1, void *lamI_n, double *lamT_n, void *work,
+                    double *grad_kappa_a, double *grad_kappa_s);
+
+/*
  * Radiation moments per cell (Sec. 2.5):
  *   R_tet  [cells][10]  R^{a^ b^} = sum_n I n^{a^} n^{b^} dOmega, pairs
  *                       00 01 02 03 11 12 13 22 23 33 (tetrad frame)

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpaper_rt.so")
 SOURCES = ["csrc/rt_api.cpp", "csrc/rt_geodesic.cpp", "csrc/rt_geometry.cpp",
-           "csrc/k_step.hip", "csrc/k_march.hip"]
+           "csrc/k_step.hip", "csrc/k_march.hip",
+           "csrc/k_adjoint.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,321 @@
+// Hand-written adjoint of one radiation step (the reverse of k_step).
+//
+// Forward step s:  I* = L(I_s)  (transport, Sec. 2.3-2.4, 2.6),
+//                  (I+, T+) = coupling(I*, T_s)  (Sec. 2.5),
+//                  beam cells re-imposed,  J += w * dt * l(I_s).
+// Given lamI = dJ/dI_{s+1}, lamT = dJ/dT_{s+1}, the adjoint step produces
+// dJ/dI_s, dJ/dT_s and accumulates dJ/dkappa_a, dJ/dkappa_s, in two kernels:
+//
+//   k_adj_couple   (one wavefront per cell) recomputes I* and the forward
+//                  coupling, then reverses it: the quartic root by the
+//                  implicit-function theorem dT+/dB_k = -T+^k / P'(T+), the
+//                  FP64 angle sums by their own adjoint sums.  Writes
+//                  psi = (dJ/dI*) / (n^0 n_0) per cell-direction.
+//   k_adj_transport (one lane per cell-direction) gathers over the faces
+//                  whose upwind value depends on the cell (radius 2): the
+//                  direct term, the upwind PLM fluxes with the van Leer
+//                  limiter's Jacobian on the branch the forward took, the
+//                  angular upwind fluxes, and the luminosity seed.
+#include <hip/hip_runtime.h>
+
+#include "k_transport.h"
+
+namespace rt {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kCellsPerBlock = 16;
+
+template <typename Real, int NCH>
+__global__ __launch_bounds__(kBlock) void k_adj_couple(
+    DevGrid G, const Real *__restrict__ Iin, const double *__restrict__ Tin,
+    const double *__restrict__ rho, const double *__restrict__ uvec,
+    const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt,
+    const Real *__restrict__ lamI1, const double *__restrict__ lamT1, Real *__restrict__ psi,
+    double *__restrict__ lamT0, double *__restrict__ gka, double *__restrict__ gks) {
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const long long ncell = (long long)G.n0 * G.n1 * G.n2;
+    const int N = G.nang;
+    const Real *q = static_cast<const Real *>(G.q);
+    const Real *invV = static_cast<const Real *>(G.invV);
+    const Real dtR = Real(dt);
+    double dummy_l = 0.0, dummy_m = 0.0;
+
+    for (int cw = wave; cw < kCellsPerBlock; cw += kWavesPerBlock) {
+        const long long cc = (long long)blockIdx.x * kCellsPerBlock + cw;
+        if (cc >= ncell) break;
+        const Cell x = make_cell(G, cc);
+        const Real ivol = invV[x.gc];
+        Real Is[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = lane + kWave * ch;
+            Is[ch] = Real(0);
+            if (n < N) Is[ch] = transport_dir(G, Iin, x, n, dtR, ivol, dummy_l, dummy_m);
+        }
+        // forward coupling, recomputed
+        const double u1 = uvec[3 * x.c], u2 = uvec[3 * x.c + 1], u3 = uvec[3 * x.c + 2];
+        const double u0 = sqrt(1.0 + u1 * u1 + u2 * u2 + u3 * u3);
+        const double rh = rho[x.c];
+        const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh, aE = aa + as;
+        const double n0 = G.n0u[x.gc];
+        double Em = 0.0, A1 = 0.0, A2 = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = lane + kWave * ch;
+            if (n >= N || G.mask[(size_t)x.gc * N + n]) continue;
+            const double nb = u0 - (u1 * G.nhat[3 * n] + u2 * G.nhat[3 * n + 1] + u3 * G.nhat[3 * n + 2]);
+            const double dn = n0 + nb * aE * dt;
+            const double w = nb * nb * G.domega[n];
+            const double I = (double)Is[ch];
+            Em += I * w;
+            A1 += (n0 / dn) * I * w;
+            A2 += G.domega[n] / (nb * dn);
+        }
+        Em = group_sum<kWave>(Em);
+        A1 = group_sum<kWave>(A1);
+        A2 = group_sum<kWave>(A2) * (dt / kFourPi);
+        const double Tm = Tin[x.c];
+        const double B4 = A2 * aa * G.a_rad;
+        const double B1 = rh * G.cv * (1.0 - A2 * as);
+        const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
+        int bad = 0;
+        const double Tp = quartic_root(B4, B1, B0, bad);
+        const double Ep = Em - rh * G.cv * (Tp - Tm);
+        const double Tp3 = Tp * Tp * Tp;
+        const double S = aa * G.a_rad * Tp3 * Tp + as * Ep;
+        const double Pp = 4.0 * B4 * Tp3 + B1;
+        // adjoint sums over directions
+        const bool beam_cell = G.beam != nullptr && G.beam[x.c];
+        double lS = 0.0, X1 = 0.0, X2 = 0.0, X3 = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = lane + kWave * ch;
+            if (n >= N || G.mask[(size_t)x.gc * N + n]) continue;
+            const double nb = u0 - (u1 * G.nhat[3 * n] + u2 * G.nhat[3 * n + 1] + u3 * G.nhat[3 * n + 2]);
+            const double dn = n0 + nb * aE * dt;
+            const double k = n0 / dn;
+            const double gdir = dt / (kFourPi * dn * nb * nb * nb);
+            const double w = nb * nb * G.domega[n];
+            const double I = (double)Is[ch];
+            const double lp = (beam_cell && n == G.beam_angle) ? 0.0 : (double)lamI1[x.c * N + n];
+            lS += lp * gdir;
+            X1 += lp * (I * k + S * gdir) * nb / dn;
+            X2 += w * I * k * nb / dn;
+            X3 += G.domega[n] / (dn * dn);
+        }
+        lS = group_sum<kWave>(lS);
+        X1 = group_sum<kWave>(X1);
+        X2 = group_sum<kWave>(X2);
+        X3 = group_sum<kWave>(X3);
+        // scalar reverse of S, Ep, the quartic and the B coefficients
+        const double rcv = rh * G.cv;
+        const double lEp = lS * as;
+        const double lTp = lamT1[x.c] + lS * 4.0 * aa * G.a_rad * Tp3 - rcv * lEp;
+        double lTm = rcv * lEp;
+        double laa = lS * G.a_rad * Tp3 * Tp;
+        double las = lS * Ep;
+        const double lB4 = -lTp * Tp3 * Tp / Pp;
+        double lB1 = -lTp * Tp / Pp;
+        const double lB0 = -lTp / Pp;
+        const double lA1 = lB0;
+        lB1 -= lB0 * Tm;
+        lTm -= lB0 * B1;
+        double lA2as = lB0 * Em;
+        const double lEm = lEp - lB0 * (1.0 - A2 * as);
+        lA2as -= rcv * lB1;
+        double lA2 = lB4 * aa * G.a_rad;
+        laa += lB4 * A2 * G.a_rad;
+        lA2 += lA2as * as;
+        las += lA2as * A2;
+        const double ltau = -X1 - lA1 * X2 - lA2 * (dt / kFourPi) * X3;
+        laa += ltau * dt;
+        las += ltau * dt;
+        // dJ/dI* per direction, divided by n^0 n_0
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = lane + kWave * ch;
+            if (n >= N) continue;
+            Real out = Real(0);
+            if (!G.mask[(size_t)x.gc * N + n]) {
+                const double nb = u0 - (u1 * G.nhat[3 * n] + u2 * G.nhat[3 * n + 1] + u3 * G.nhat[3 * n + 2]);
+                const double dn = n0 + nb * aE * dt;
+                const double k = n0 / dn;
+                const double w = nb * nb * G.domega[n];
+                const double lp = (beam_cell && n == G.beam_angle) ? 0.0 : (double)lamI1[x.c * N + n];
+                const double lstar = k * lp + (lEm + lA1 * k) * w;
+                out = Real(lstar / (double)q[(size_t)x.gc * N + n]);
+            }
+            psi[x.c * N + n] = out;
+        }
+        if (lane == 0) {
+            lamT0[x.c] = lTm;
+            if (gka) gka[x.c] += laa * rh;
+            if (gks) gks[x.c] += las * rh;
+        }
+    }
+}
+
+// psi of direction n in the cell `o` steps along axis a from x, zero outside
+// a non-periodic domain; also that cell's 1/dV
+template <typename Real>
+__device__ __forceinline__ Real psi_at(const DevGrid &G, const Real *__restrict__ psi,
+                                       const Cell &x, int a, int o, int n, Real &ivol) {
+    const Real *invV = static_cast<const Real *>(G.invV);
+    const int coord = axis_coord(x, a);
+    const int len = axis_len(G, a);
+    int idx = coord + o;
+    if (idx < 0 || idx >= len) {
+        if (G.bc[a][idx < 0 ? 0 : 1] != RT_BC_PERIODIC) {
+            ivol = Real(0);
+            return Real(0);
+        }
+        idx = ((idx % len) + len) % len;
+    }
+    const long long c = x.c + (long long)(idx - coord) * axis_stride(G, a);
+    const Cell y = make_cell(G, c);
+    ivol = invV[y.gc];
+    return psi[c * G.nang + n];
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real *__restrict__ Iin,
+                                                          const Real *__restrict__ psi, double dt,
+                                                          double lum_weight,
+                                                          Real *__restrict__ lamI0) {
+    const long long ncell = (long long)G.n0 * G.n1 * G.n2;
+    const int N = G.nang;
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= ncell * N) return;
+    const int n = (int)(t % N);
+    const Cell x = make_cell(G, t / N);
+    const Real *q = static_cast<const Real *>(G.q);
+    const Real *vw = static_cast<const Real *>(G.vw);
+    const Real dtR = Real(dt);
+    const bool plm = G.recon == RT_RECON_PLM;
+
+    // direct term: I*_c = I_c - (flux terms)
+    Real lam = G.mask[(size_t)x.gc * N + n] ? Real(0) : psi[x.c * N + n] * q[(size_t)x.gc * N + n];
+
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int coord = axis_coord(x, a);
+        const int len = axis_len(G, a);
+        const bool periodic = G.bc[a][0] == RT_BC_PERIODIC;
+        const Real *C = static_cast<const Real *>(G.C[a]);
+        Real v[5];
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) v[o + 2] = nbr(G, Iin, x, a, o, n);
+        Real ps[5], iv[5];   // psi and 1/dV of cells at offsets -2 .. 2
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) ps[o + 2] = psi_at(G, psi, x, a, o, n, iv[o + 2]);
+        // faces at offsets fo = -1 .. 2 (face F between cells F-1 and F)
+#pragma unroll
+        for (int fo = -1; fo <= 2; ++fo) {
+            const int Fraw = coord + fo;
+            if (!periodic && (Fraw < 0 || Fraw > len)) continue;
+            const int F = periodic ? ((Fraw % len) + len) % len : Fraw;
+            const int fg = face_geo(G, a, F, x);
+            const int s = G.sgn[a][(size_t)fg * N + n];
+            if (s == 0) continue;
+            const int u = s > 0 ? fo - 1 : fo;       // upwind cell, relative to x
+            if (u < -1 || u > 1) continue;
+            if (!periodic && (coord + u < 0 || coord + u >= len)) continue;  // ghost upwind
+            // d I_up / d I_x, I_up = I_u +- delta_u / 2
+            Real d = u == 0 ? Real(1) : Real(0);
+            if (plm) {
+                const Real dm = v[u + 2] - v[u + 1], dp = v[u + 3] - v[u + 2];
+                const Real prod = dm * dp;
+                if (prod > Real(0)) {
+                    const Real den = dm + dp;
+                    const Real Dm = Real(2) * dp * dp / (den * den);   // d delta / d dm
+                    const Real Dp = Real(2) * dm * dm / (den * den);   // d delta / d dp
+                    // position of x in (u-1, u, u+1)
+                    const Real dd = u == 1 ? -Dm : (u == 0 ? Dm - Dp : Dp);
+                    d += (s > 0 ? Real(0.5) : Real(-0.5)) * dd;
+                }
+            }
+            // dJ/dF: the face is the upper face of cell fo-1 and the lower face of cell fo
+            Real lF = dtR * (ps[fo + 2] * iv[fo + 2] - ps[fo + 1] * iv[fo + 1]);
+            // luminosity face (on a periodic axis the face between the last
+            // and the first cell, where the forward step counts it)
+            if (a == G.lum_axis) {
+                const bool on = periodic ? F == 0 : (G.lum_side == 1 ? F == len : F == 0);
+                if (on) lF += Real((G.lum_side == 1 ? -1.0 : 1.0) * lum_weight * dt * G.domega[n]);
+            }
+            lam += lF * C[(size_t)fg * N + n] * d;
+        }
+    }
+    if (G.has_edges) {
+#pragma unroll
+        for (int s = 0; s < kMaxNbr; ++s) {
+            const int e = G.adj_e[n * kMaxNbr + s];
+            if (e < 0) break;
+            const size_t vi = ((size_t)x.gc * G.nedge + e) * 2;
+            const Real vv = vw[vi], ww = vw[vi + 1];
+            const bool up = G.adj_s[n * kMaxNbr + s] > 0 ? vv > Real(0) : vv < Real(0);
+            if (!up) continue;
+            const int lo = G.edge_lo[e], hi = G.edge_hi[e];
+            const Real lF = -dtR * (psi[x.c * N + lo] / Real(G.domega[lo]) -
+                                    psi[x.c * N + hi] / Real(G.domega[hi]));
+            lam += lF * ww;
+        }
+    }
+    lamI0[x.c * N + n] = lam;
+}
+
+template <typename Real>
+int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
+                 const double *rho, const double *u, const double *ka, const double *ks,
+                 double dt, double lum_weight, const void *lamI1, const double *lamT1,
+                 void *lamI0, double *lamT0, void *work, double *gka, double *gks) {
+    const DevGrid &G = g->dg;
+    const long long ncell = (long long)G.n0 * G.n1 * G.n2;
+    const int nblk = (int)((ncell + kCellsPerBlock - 1) / kCellsPerBlock);
+    const int nch = (G.nang + kWave - 1) / kWave;
+    const Real *in = static_cast<const Real *>(Iin);
+    const Real *l1 = static_cast<const Real *>(lamI1);
+    Real *psi = static_cast<Real *>(work);
+#define RT_LAUNCH(NC)                                                                          \
+    case NC:                                                                                   \
+        hipLaunchKernelGGL((k_adj_couple<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in,   \
+                           Tin, rho, u, ka, ks, dt, l1, lamT1, psi, lamT0, gka, gks);          \
+        break;
+    switch (nch) {
+        RT_LAUNCH(1)
+        RT_LAUNCH(2)
+        RT_LAUNCH(3)
+        RT_LAUNCH(4)
+        RT_LAUNCH(5)
+        RT_LAUNCH(6)
+        RT_LAUNCH(7)
+        RT_LAUNCH(8)
+        default:
+            return RT_EINVAL;
+    }
+#undef RT_LAUNCH
+    if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
+    const long long tot = ncell * G.nang;
+    const int nb2 = (int)((tot + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_adj_transport<Real>, dim3(nb2), dim3(kBlock), 0, s, G, in,
+                       static_cast<const Real *>(psi), dt, lum_weight,
+                       static_cast<Real *>(lamI0));
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
+}
+
+}  // namespace
+
+int launch_adjoint(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
+                   const double *rho, const double *u, const double *ka, const double *ks,
+                   double dt, double lum_weight, const void *lamI1, const double *lamT1,
+                   void *lamI0, double *lamT0, void *work, double *gka, double *gks) {
+    if (g->precision == RT_F32)
+        return launch_adj_t<float>(g, s, Iin, Tin, rho, u, ka, ks, dt, lum_weight, lamI1, lamT1,
+                                   lamI0, lamT0, work, gka, gks);
+    return launch_adj_t<double>(g, s, Iin, Tin, rho, u, ka, ks, dt, lum_weight, lamI1, lamT1,
+                                lamI0, lamT0, work, gka, gks);
+}
+
+}  // namespace rt

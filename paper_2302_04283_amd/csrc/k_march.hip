@@ -450,7 +450,7 @@ bool march_config(int precision, int nang, int &sw, int &nc) {
     const int (*tab)[2] = precision == RT_F32 ? f32 : f64;
     const int ntab = precision == RT_F32 ? 9 : 6;
     // smallest group width whose directions-per-lane fits the register budget
-    const int budget = precision == RT_F32 ? 6 : 3;
+    const int budget = 6;
     for (int w : {16, 32, 64}) {
         if (want && w != want) continue;
         const int need = (nang + w - 1) / w;

@@ -1,0 +1,139 @@
+// Per-direction transport of the general step kernel (paper Sec. 2.3-2.4,
+// 2.6), shared by the forward step and the adjoint (which recomputes I*).
+#pragma once
+
+#include "k_common.h"
+
+namespace rt {
+
+struct Cell {
+    int i, j, k;     // cell coordinates
+    long long c;     // linear cell index
+    int gc;          // geometry cell index
+};
+
+__device__ __forceinline__ Cell make_cell(const DevGrid &G, long long c) {
+    Cell x;
+    x.c = c;
+    x.i = (int)(c % G.n0);
+    x.j = (int)((c / G.n0) % G.n1);
+    x.k = (int)(c / ((long long)G.n0 * G.n1));
+    x.gc = ((G.g2 > 1 ? x.k : 0) * G.g1 + (G.g1 > 1 ? x.j : 0)) * G.g0 + (G.g0 > 1 ? x.i : 0);
+    return x;
+}
+
+__device__ __forceinline__ int face_geo(const DevGrid &G, int a, int fidx, const Cell &x) {
+    const int xi = (a == 0) ? (G.fe[a][0] > 1 ? fidx : 0) : (G.g0 > 1 ? x.i : 0);
+    const int xj = (a == 1) ? (G.fe[a][1] > 1 ? fidx : 0) : (G.g1 > 1 ? x.j : 0);
+    const int xk = (a == 2) ? (G.fe[a][2] > 1 ? fidx : 0) : (G.g2 > 1 ? x.k : 0);
+    return (xk * G.fe[a][1] + xj) * G.fe[a][0] + xi;
+}
+
+__device__ __forceinline__ int axis_coord(const Cell &x, int a) {
+    return a == 0 ? x.i : (a == 1 ? x.j : x.k);
+}
+__device__ __forceinline__ int axis_len(const DevGrid &G, int a) {
+    return a == 0 ? G.n0 : (a == 1 ? G.n1 : G.n2);
+}
+__device__ __forceinline__ long long axis_stride(const DevGrid &G, int a) {
+    return a == 0 ? 1LL : (a == 1 ? (long long)G.n0 : (long long)G.n0 * G.n1);
+}
+
+// Intensity of direction n in the cell `o` steps along axis a from x, with
+// boundary conditions applied: periodic wrap, or (outflow/vacuum) a copy of
+// the adjacent active cell for directions leaving the domain through that
+// boundary face and zero for directions entering it.
+template <typename Real>
+__device__ __forceinline__ Real nbr(const DevGrid &G, const Real *__restrict__ I, const Cell &x,
+                                    int a, int o, int n) {
+    const int coord = axis_coord(x, a);
+    const int len = axis_len(G, a);
+    const long long stride = axis_stride(G, a);
+    const int idx = coord + o;
+    if (idx >= 0 && idx < len) return I[(x.c + (long long)o * stride) * G.nang + n];
+    const int side = idx < 0 ? 0 : 1;
+    if (G.bc[a][side] == RT_BC_PERIODIC) {
+        const int w = ((idx % len) + len) % len;
+        return I[(x.c + (long long)(w - coord) * stride) * G.nang + n];
+    }
+    const int fg = face_geo(G, a, side ? len : 0, x);
+    const int s = G.sgn[a][(size_t)fg * G.nang + n];
+    const bool out = side ? (s > 0) : (s < 0);
+    if (!out) return Real(0);
+    const int edge = side ? len - 1 : 0;
+    return I[(x.c + (long long)(edge - coord) * stride) * G.nang + n];
+}
+
+template <typename Real>
+__device__ __forceinline__ Real van_leer(Real dm, Real dp) {
+    Real prod = dm * dp;
+    return prod > Real(0) ? Real(2) * prod / (dm + dp) : Real(0);
+}
+
+// I* of direction n in cell x after the flux divergence (Sec. 2.2 gray
+// integral form) and primitive recovery, zero where masked.  Adds the
+// luminosity-face and masked-energy contributions to the accumulators.
+template <typename Real>
+__device__ __forceinline__ Real transport_dir(const DevGrid &G, const Real *__restrict__ Iin,
+                                              const Cell &x, int n, Real dtR, Real ivol,
+                                              double &lum_acc, double &me_acc) {
+    const int N = G.nang;
+    const Real *q = static_cast<const Real *>(G.q);
+    const Real *vw = static_cast<const Real *>(G.vw);
+    const Real Ic = Iin[x.c * N + n];
+    Real dq = Real(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int coord = axis_coord(x, a);
+        const int len = axis_len(G, a);
+        Real v[5];
+        v[2] = Ic;
+        v[1] = nbr(G, Iin, x, a, -1, n);
+        v[3] = nbr(G, Iin, x, a, +1, n);
+        Real dlm = Real(0), dl0 = Real(0), dlp = Real(0);
+        if (G.recon == RT_RECON_PLM) {
+            v[0] = nbr(G, Iin, x, a, -2, n);
+            v[4] = nbr(G, Iin, x, a, +2, n);
+            dlm = van_leer(v[1] - v[0], v[2] - v[1]);
+            dl0 = van_leer(v[2] - v[1], v[3] - v[2]);
+            dlp = van_leer(v[3] - v[2], v[4] - v[3]);
+        }
+        const int flo = face_geo(G, a, coord, x);
+        const int fhi = face_geo(G, a, coord + 1, x);
+        const Real *C = static_cast<const Real *>(G.C[a]);
+        const int slo = G.sgn[a][(size_t)flo * N + n];
+        const int shi = G.sgn[a][(size_t)fhi * N + n];
+        const Real ulo = slo > 0 ? v[1] + Real(0.5) * dlm : (slo < 0 ? v[2] - Real(0.5) * dl0 : Real(0));
+        const Real uhi = shi > 0 ? v[2] + Real(0.5) * dl0 : (shi < 0 ? v[3] - Real(0.5) * dlp : Real(0));
+        const Real Flo = C[(size_t)flo * N + n] * ulo;
+        const Real Fhi = C[(size_t)fhi * N + n] * uhi;
+        dq += Fhi - Flo;
+        if (a == G.lum_axis) {
+            if (G.lum_side == 1 && coord == len - 1) lum_acc -= G.domega[n] * (double)Fhi;
+            if (G.lum_side == 0 && coord == 0) lum_acc += G.domega[n] * (double)Flo;
+        }
+    }
+    Real div = Real(0);
+    if (G.has_edges) {
+#pragma unroll
+        for (int s = 0; s < kMaxNbr; ++s) {
+            const int e = G.adj_e[n * kMaxNbr + s];
+            if (e < 0) break;
+            const size_t vi = ((size_t)x.gc * G.nedge + e) * 2;
+            const Real vv = vw[vi], ww = vw[vi + 1];
+            const Real up = vv > Real(0) ? Iin[x.c * N + G.edge_lo[e]]
+                                         : (vv < Real(0) ? Iin[x.c * N + G.edge_hi[e]] : Real(0));
+            const Real F = ww * up;
+            div += G.adj_s[n * kMaxNbr + s] > 0 ? F : -F;
+        }
+    }
+    const Real qn = q[(size_t)x.gc * N + n];
+    const Real Qs = qn * Ic - dtR * ivol * dq - dtR * div / Real(G.domega[n]);
+    if (G.mask[(size_t)x.gc * N + n]) {
+        me_acc -= G.volD[x.gc] * G.domega[n] * (double)Qs;
+        return Real(0);
+    }
+    return Qs / qn;
+}
+
+}  // namespace rt

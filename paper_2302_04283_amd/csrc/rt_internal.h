@@ -131,4 +131,8 @@ int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double 
                  const double *rho, const double *u, const double *ka, const double *ks,
                  double dt, double *dT0);
 int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *lum);
+int launch_adjoint(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
+                   const double *rho, const double *u, const double *ka, const double *ks,
+                   double dt, double lum_weight, const void *lamI1, const double *lamT1,
+                   void *lamI0, double *lamT0, void *work, double *gka, double *gks);
 }  // namespace rt

@@ -76,12 +76,14 @@ def load():
     lib.rt_max_dt.argtypes = [vp, C.c_double, _dp]
     lib.rt_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
     lib.rt_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.rt_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double,
+                                    vp, vp, vp, vp, vp, vp, vp]
     lib.rt_stats.argtypes = [vp, C.POINTER(C.c_int64), _dp]
     lib.rt_free.argtypes = [vp]
     lib.rt_free.restype = None
     lib.rt_last_error.restype = C.c_char_p
     for f in ("rt_init_grid", "rt_geodesic_angles", "rt_grid_info", "rt_angles",
-              "rt_max_dt", "rt_step", "rt_moments", "rt_stats"):
+              "rt_max_dt", "rt_step", "rt_moments", "rt_stats", "rt_step_adjoint"):
         getattr(lib, f).restype = C.c_int
     _LIB = lib
     return lib
@@ -233,6 +235,28 @@ class Grid:
         _check(self._lib.rt_step(self._h, C.c_void_p(s.cuda_stream), _dev(I_in), _dev(I_out),
                                  _dev(T), _dev(rho), _dev(u), _dev(kappa_a), _dev(kappa_s),
                                  float(dt), _dev(dT0), _dev(lum)))
+
+    def step_adjoint(self, I_n, T_n, rho, u, kappa_a, kappa_s, dt, lamI_next, lamT_next,
+                     lamI_out, lamT_out, work, grad_kappa_a=None, grad_kappa_s=None,
+                     lum_weight=1.0, stream=None):
+        """Reverse of step() for J = sum dt * luminosity; see rt_step_adjoint."""
+        import torch
+        rd = self.real_dtype()
+        f8 = torch.float64
+        for t, name in ((I_n, "I_n"), (lamI_next, "lamI_next"), (lamI_out, "lamI_out"),
+                        (work, "work")):
+            self._need(t, self._state_shape(), rd, name)
+        for t, name in ((T_n, "T_n"), (rho, "rho"), (kappa_a, "kappa_a"), (kappa_s, "kappa_s"),
+                        (lamT_next, "lamT_next"), (lamT_out, "lamT_out"),
+                        (grad_kappa_a, "grad_kappa_a"), (grad_kappa_s, "grad_kappa_s")):
+            self._need(t, self._cell_shape(), f8, name)
+        self._need(u, self._cell_shape(3), f8, "u")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(self._lib.rt_step_adjoint(
+            self._h, C.c_void_p(s.cuda_stream), _dev(I_n), _dev(T_n), _dev(rho), _dev(u),
+            _dev(kappa_a), _dev(kappa_s), float(dt), float(lum_weight), _dev(lamI_next),
+            _dev(lamT_next), _dev(lamI_out), _dev(lamT_out), _dev(work), _dev(grad_kappa_a),
+            _dev(grad_kappa_s)))
 
     def moments(self, I, u=None, stream=None):
         import torch

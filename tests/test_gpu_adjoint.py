@@ -1,0 +1,134 @@
+"""The hand-written adjoint (rt_step_adjoint through RadTransport) against the
+oracle's reference gradient and against central finite differences.
+
+Tolerances: FP64 adjoint vs the oracle's autograd gradient 1e-10 in max-norm
+relative to max|g|; FP32 adjoint 1e-4; FP64 adjoint vs central differences
+(h = 1e-6 relative) 1e-5 relative on cells with a non-negligible gradient,
+plus the cancellation floor of a central difference, 4e-15 |J| / h (the two
+perturbed runs each carry ~1e-15 |J| of rounding in their FP64 sums).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gradient as GR
+from oracle import step as O
+from paper_2302_04283_amd import rt
+from paper_2302_04283_amd import workloads as W
+from paper_2302_04283_amd.autograd import luminosity_and_gradients
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(DEV)
+
+
+def _gpu_grads(p, prec, steps, dt, K, I0=None, T0=None):
+    g = rt.Grid(p, prec)
+    I0 = p.initial_intensity() if I0 is None else I0
+    T0 = p.T if T0 is None else T0
+    J, gI, gT, gka, gks = luminosity_and_gradients(
+        g, _t(I0).to(g.real_dtype()), _t(T0), _t(p.kappa_a), _t(p.kappa_s), _t(p.rho),
+        _t(p.u_tet), dt, steps, K)
+    out = {"J": float(J), "I0": gI.double().cpu().numpy(), "T0": gT.cpu().numpy(),
+           "kappa_a": gka.cpu().numpy(), "kappa_s": gks.cpu().numpy()}
+    g.close()
+    return out
+
+
+def _max_rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("cfg,scale,steps,K", [("c4", (12, 8, 6), 6, 4), ("c3", (10, 8, 4), 4, 2),
+                                               ("c2", (8, 8, 8), 5, 2)])
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+def test_adjoint_matches_reference_gradient(cfg, scale, steps, K, prec):
+    p = W.make_problem(cfg, scale=scale)
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    ref = GR.reference_gradient(p, p.initial_intensity(), p.T, dt, steps)
+    got = _gpu_grads(p, prec, steps, dt, K)
+    tol = 1e-10 if prec == rt.RT_F64 else 1e-4
+    errs = {k: _max_rel(got[k], ref[k]) for k in ("kappa_a", "kappa_s", "T0", "I0")}
+    eJ = abs(got["J"] - ref["J"]) / abs(ref["J"])
+    print("[adjoint] %s %s %s steps=%d K=%d e_J=%.2e %s" % (
+        cfg, scale, "fp64" if prec == rt.RT_F64 else "fp32", steps, K, eJ,
+        " ".join("e_%s=%.2e" % kv for kv in errs.items())), flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
+def test_adjoint_checkpoint_interval_does_not_change_gradients():
+    p = W.make_problem("c4", scale=(12, 8, 6))
+    dt = O.max_dt(O.setup(p), 0.3)
+    a = _gpu_grads(p, rt.RT_F64, 7, dt, 1)
+    b = _gpu_grads(p, rt.RT_F64, 7, dt, 7)
+    c = _gpu_grads(p, rt.RT_F64, 7, dt, 3)
+    for k in ("kappa_a", "T0", "I0"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k])
+
+
+def test_adjoint_full_c4_central_differences():
+    """64x32x64, 92 directions, 50 steps, checkpoint every 10 steps (FP64):
+    16 kappa_a cells and 16 T0 cells among those with |g| >= 1e-3 max|g|
+    whose central-difference signal |g| h is resolvable (>= 1e-9 |J|), plus,
+    as controls, the 4 cells with the smallest |g| (their central difference
+    must be negligible against max|g|)."""
+    p = W.make_problem("c4")
+    dt = O.max_dt(O.setup(p), p.cfl)
+    steps, K = p.nsteps, 10
+    got = _gpu_grads(p, rt.RT_F64, steps, dt, K)
+    g = rt.Grid(p, rt.RT_F64)
+    I0 = _t(p.initial_intensity())
+    rho, u, ks = _t(p.rho), _t(p.u_tet), _t(p.kappa_s)
+
+    def J_of(ka, T0):
+        I = I0.clone()
+        Ib = torch.empty_like(I)
+        T = T0.clone()
+        lum = torch.zeros(1, dtype=torch.float64, device=DEV)
+        for _ in range(steps):
+            g.step(I, Ib, T, rho, u, ka, ks, dt, None, lum)
+            I, Ib = Ib, I
+        return float(lum[0])
+
+    J0 = got["J"]
+    rng = np.random.default_rng(4)
+    worst = 0.0
+    for key in ("kappa_a", "T0"):
+        G = got[key]
+        hh = 1e-6 * (p.kappa_a if key == "kappa_a" else p.T)
+        ok = ((np.abs(G) >= 1e-3 * np.abs(G).max()) & (np.abs(G) * hh >= 1e-9 * abs(J0))).ravel()
+        big = np.flatnonzero(ok)
+        assert big.size >= 8, (key, big.size)
+        pick = rng.choice(big, size=min(16, big.size), replace=False)
+        small = np.argsort(np.abs(G).ravel())[:4]
+        gmax = np.abs(G).max()
+        for flat in np.concatenate([pick, small]):
+            c = np.unravel_index(flat, G.shape)
+            base_ka = _t(p.kappa_a)
+            base_T = _t(p.T)
+            if key == "kappa_a":
+                h = 1e-6 * p.kappa_a[c]
+                kp, km = base_ka.clone(), base_ka.clone()
+                kp[c] += h
+                km[c] -= h
+                fd = (J_of(kp, base_T) - J_of(km, base_T)) / (2 * h)
+            else:
+                h = 1e-6 * p.T[c]
+                tp, tm = base_T.clone(), base_T.clone()
+                tp[c] += h
+                tm[c] -= h
+                fd = (J_of(base_ka, tp) - J_of(base_ka, tm)) / (2 * h)
+            floor = 4e-15 * abs(J0) / h
+            if flat in small:
+                assert abs(fd - G[c]) <= 1e-6 * gmax + floor, (key, c, G[c], fd)
+            else:
+                e = abs(G[c] - fd) / abs(G[c])
+                worst = max(worst, e)
+                assert abs(G[c] - fd) <= 1e-5 * abs(G[c]) + floor, (key, c, G[c], fd, floor)
+    print("[adjoint] c4 full 64x32x64x92 50 steps K=10: worst FD rel err %.2e" % worst, flush=True)
+    g.close()
