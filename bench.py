@@ -167,7 +167,20 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--checkpoint-every", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the "
+                         "reference for scaling HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 256 * 1024 * 1024
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the radiation step is built and timed on a "
               "single MI355X (see DESIGN.md for how it would shard); --gpus %d is not "

@@ -158,112 +158,120 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     }
 }
 
-// psi of direction n in the cell `o` steps along axis a from x, zero outside
-// a non-periodic domain; also that cell's 1/dV
-template <typename Real>
-__device__ __forceinline__ Real psi_at(const DevGrid &G, const Real *__restrict__ psi,
-                                       const Cell &x, int a, int o, int n, Real &ivol) {
-    const Real *invV = static_cast<const Real *>(G.invV);
-    const int coord = axis_coord(x, a);
-    const int len = axis_len(G, a);
-    int idx = coord + o;
-    if (idx < 0 || idx >= len) {
-        if (G.bc[a][idx < 0 ? 0 : 1] != RT_BC_PERIODIC) {
-            ivol = Real(0);
-            return Real(0);
-        }
-        idx = ((idx % len) + len) % len;
-    }
-    const long long c = x.c + (long long)(idx - coord) * axis_stride(G, a);
-    const Cell y = make_cell(G, c);
-    ivol = invV[y.gc];
-    return psi[c * G.nang + n];
+// Geometry-cell stride along axis a (0 if the geometry does not depend on a).
+__device__ __forceinline__ int geo_stride(const DevGrid &G, int a) {
+    if (a == 0) return G.g0 > 1 ? 1 : 0;
+    if (a == 1) return G.g1 > 1 ? G.g0 : 0;
+    return G.g2 > 1 ? G.g0 * G.g1 : 0;
 }
 
-template <typename Real>
+template <typename Real, int NCH>
 __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real *__restrict__ Iin,
                                                           const Real *__restrict__ psi, double dt,
                                                           double lum_weight,
                                                           Real *__restrict__ lamI0) {
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
     const long long ncell = (long long)G.n0 * G.n1 * G.n2;
     const int N = G.nang;
-    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= ncell * N) return;
-    const int n = (int)(t % N);
-    const Cell x = make_cell(G, t / N);
     const Real *q = static_cast<const Real *>(G.q);
     const Real *vw = static_cast<const Real *>(G.vw);
+    const Real *invV = static_cast<const Real *>(G.invV);
     const Real dtR = Real(dt);
     const bool plm = G.recon == RT_RECON_PLM;
 
-    // direct term: I*_c = I_c - (flux terms)
-    Real lam = G.mask[(size_t)x.gc * N + n] ? Real(0) : psi[x.c * N + n] * q[(size_t)x.gc * N + n];
-
+    for (int cw = wave; cw < kCellsPerBlock; cw += kWavesPerBlock) {
+        const long long cc = (long long)blockIdx.x * kCellsPerBlock + cw;
+        if (cc >= ncell) break;
+        const Cell x = make_cell(G, cc);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int coord = axis_coord(x, a);
-        const int len = axis_len(G, a);
-        const bool periodic = G.bc[a][0] == RT_BC_PERIODIC;
-        const Real *C = static_cast<const Real *>(G.C[a]);
-        Real v[5];
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = lane + kWave * ch;
+            if (n >= N) continue;
+            // direct term: I*_c = I_c - (flux terms)
+            Real lam = G.mask[(size_t)x.gc * N + n] ? Real(0) : psi[x.c * N + n] * q[(size_t)x.gc * N + n];
 #pragma unroll
-        for (int o = -2; o <= 2; ++o) v[o + 2] = nbr(G, Iin, x, a, o, n);
-        Real ps[5], iv[5];   // psi and 1/dV of cells at offsets -2 .. 2
+            for (int a = 0; a < 3; ++a) {
+                const int coord = axis_coord(x, a);
+                const int len = axis_len(G, a);
+                const long long stride = axis_stride(G, a);
+                const int gstr = geo_stride(G, a);
+                const bool periodic = G.bc[a][0] == RT_BC_PERIODIC;
+                const Real *C = static_cast<const Real *>(G.C[a]);
+                Real v[5], ps[5], iv[5];
 #pragma unroll
-        for (int o = -2; o <= 2; ++o) ps[o + 2] = psi_at(G, psi, x, a, o, n, iv[o + 2]);
-        // faces at offsets fo = -1 .. 2 (face F between cells F-1 and F)
+                for (int o = -2; o <= 2; ++o) {
+                    v[o + 2] = nbr(G, Iin, x, a, o, n);
+                    int idx = coord + o;
+                    bool inside = idx >= 0 && idx < len;
+                    if (!inside && periodic) {
+                        idx = ((idx % len) + len) % len;
+                        inside = true;
+                    }
+                    if (inside) {
+                        const long long c = x.c + (long long)(idx - coord) * stride;
+                        ps[o + 2] = psi[c * N + n];
+                        iv[o + 2] = invV[x.gc + (idx - coord) * gstr];
+                    } else {
+                        ps[o + 2] = Real(0);
+                        iv[o + 2] = Real(0);
+                    }
+                }
+                // faces at offsets fo = -1 .. 2 (face F between cells F-1 and F)
 #pragma unroll
-        for (int fo = -1; fo <= 2; ++fo) {
-            const int Fraw = coord + fo;
-            if (!periodic && (Fraw < 0 || Fraw > len)) continue;
-            const int F = periodic ? ((Fraw % len) + len) % len : Fraw;
-            const int fg = face_geo(G, a, F, x);
-            const int s = G.sgn[a][(size_t)fg * N + n];
-            if (s == 0) continue;
-            const int u = s > 0 ? fo - 1 : fo;       // upwind cell, relative to x
-            if (u < -1 || u > 1) continue;
-            if (!periodic && (coord + u < 0 || coord + u >= len)) continue;  // ghost upwind
-            // d I_up / d I_x, I_up = I_u +- delta_u / 2
-            Real d = u == 0 ? Real(1) : Real(0);
-            if (plm) {
-                const Real dm = v[u + 2] - v[u + 1], dp = v[u + 3] - v[u + 2];
-                const Real prod = dm * dp;
-                if (prod > Real(0)) {
-                    const Real den = dm + dp;
-                    const Real Dm = Real(2) * dp * dp / (den * den);   // d delta / d dm
-                    const Real Dp = Real(2) * dm * dm / (den * den);   // d delta / d dp
-                    // position of x in (u-1, u, u+1)
-                    const Real dd = u == 1 ? -Dm : (u == 0 ? Dm - Dp : Dp);
-                    d += (s > 0 ? Real(0.5) : Real(-0.5)) * dd;
+                for (int fo = -1; fo <= 2; ++fo) {
+                    const int Fraw = coord + fo;
+                    if (!periodic && (Fraw < 0 || Fraw > len)) continue;
+                    const int F = periodic ? ((Fraw % len) + len) % len : Fraw;
+                    const int fg = face_geo(G, a, F, x);
+                    const int s = G.sgn[a][(size_t)fg * N + n];
+                    if (s == 0) continue;
+                    const int u = s > 0 ? fo - 1 : fo;       // upwind cell, relative to x
+                    if (u < -1 || u > 1) continue;
+                    if (!periodic && (coord + u < 0 || coord + u >= len)) continue;  // ghost upwind
+                    // d I_up / d I_x, I_up = I_u +- delta_u / 2
+                    Real d = u == 0 ? Real(1) : Real(0);
+                    if (plm) {
+                        const Real dm = v[u + 2] - v[u + 1], dp = v[u + 3] - v[u + 2];
+                        const Real prod = dm * dp;
+                        if (prod > Real(0)) {
+                            const Real den = dm + dp;
+                            const Real Dm = Real(2) * dp * dp / (den * den);   // d delta / d dm
+                            const Real Dp = Real(2) * dm * dm / (den * den);   // d delta / d dp
+                            // position of x in (u-1, u, u+1)
+                            const Real dd = u == 1 ? -Dm : (u == 0 ? Dm - Dp : Dp);
+                            d += (s > 0 ? Real(0.5) : Real(-0.5)) * dd;
+                        }
+                    }
+                    // dJ/dF: the face is the upper face of cell fo-1 and the lower face of cell fo
+                    Real lF = dtR * (ps[fo + 2] * iv[fo + 2] - ps[fo + 1] * iv[fo + 1]);
+                    // luminosity face (on a periodic axis the face between the last
+                    // and the first cell, where the forward step counts it)
+                    if (a == G.lum_axis) {
+                        const bool on = periodic ? F == 0 : (G.lum_side == 1 ? F == len : F == 0);
+                        if (on) lF += Real((G.lum_side == 1 ? -1.0 : 1.0) * lum_weight * dt * G.domega[n]);
+                    }
+                    lam += lF * C[(size_t)fg * N + n] * d;
                 }
             }
-            // dJ/dF: the face is the upper face of cell fo-1 and the lower face of cell fo
-            Real lF = dtR * (ps[fo + 2] * iv[fo + 2] - ps[fo + 1] * iv[fo + 1]);
-            // luminosity face (on a periodic axis the face between the last
-            // and the first cell, where the forward step counts it)
-            if (a == G.lum_axis) {
-                const bool on = periodic ? F == 0 : (G.lum_side == 1 ? F == len : F == 0);
-                if (on) lF += Real((G.lum_side == 1 ? -1.0 : 1.0) * lum_weight * dt * G.domega[n]);
-            }
-            lam += lF * C[(size_t)fg * N + n] * d;
-        }
-    }
-    if (G.has_edges) {
+            if (G.has_edges) {
 #pragma unroll
-        for (int s = 0; s < kMaxNbr; ++s) {
-            const int e = G.adj_e[n * kMaxNbr + s];
-            if (e < 0) break;
-            const size_t vi = ((size_t)x.gc * G.nedge + e) * 2;
-            const Real vv = vw[vi], ww = vw[vi + 1];
-            const bool up = G.adj_s[n * kMaxNbr + s] > 0 ? vv > Real(0) : vv < Real(0);
-            if (!up) continue;
-            const int lo = G.edge_lo[e], hi = G.edge_hi[e];
-            const Real lF = -dtR * (psi[x.c * N + lo] / Real(G.domega[lo]) -
-                                    psi[x.c * N + hi] / Real(G.domega[hi]));
-            lam += lF * ww;
+                for (int s = 0; s < kMaxNbr; ++s) {
+                    const int e = G.adj_e[n * kMaxNbr + s];
+                    if (e < 0) break;
+                    const size_t vi = ((size_t)x.gc * G.nedge + e) * 2;
+                    const Real vv = vw[vi], ww = vw[vi + 1];
+                    const bool up = G.adj_s[n * kMaxNbr + s] > 0 ? vv > Real(0) : vv < Real(0);
+                    if (!up) continue;
+                    const int lo = G.edge_lo[e], hi = G.edge_hi[e];
+                    const Real lF = -dtR * (psi[x.c * N + lo] / Real(G.domega[lo]) -
+                                            psi[x.c * N + hi] / Real(G.domega[hi]));
+                    lam += lF * ww;
+                }
+            }
+            lamI0[x.c * N + n] = lam;
         }
     }
-    lamI0[x.c * N + n] = lam;
 }
 
 template <typename Real>
@@ -297,11 +305,25 @@ int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
     }
 #undef RT_LAUNCH
     if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
-    const long long tot = ncell * G.nang;
-    const int nb2 = (int)((tot + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_adj_transport<Real>, dim3(nb2), dim3(kBlock), 0, s, G, in,
-                       static_cast<const Real *>(psi), dt, lum_weight,
-                       static_cast<Real *>(lamI0));
+#define RT_LAUNCH2(NC)                                                                         \
+    case NC:                                                                                   \
+        hipLaunchKernelGGL((k_adj_transport<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in,    \
+                           static_cast<const Real *>(psi), dt, lum_weight,                      \
+                           static_cast<Real *>(lamI0));                                         \
+        break;
+    switch (nch) {
+        RT_LAUNCH2(1)
+        RT_LAUNCH2(2)
+        RT_LAUNCH2(3)
+        RT_LAUNCH2(4)
+        RT_LAUNCH2(5)
+        RT_LAUNCH2(6)
+        RT_LAUNCH2(7)
+        RT_LAUNCH2(8)
+        default:
+            return RT_EINVAL;
+    }
+#undef RT_LAUNCH2
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
 }
 
