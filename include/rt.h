@@ -150,11 +150,15 @@ int rt_max_dt(const rt_grid *g, double cfl, double *dt);
  *         (Sec. 2.5, last paragraph); NULL to skip
  *   lum   (dev, optional) one double, += dt * (energy per unit time leaving
  *         through the luminosity face); NULL to skip
+ *   I_star (dev, optional) [n2][n1][n0][nang], grid precision: receives the
+ *         intensities after transport and before the coupling (I*, zero for
+ *         masked directions), which rt_step_adjoint can take instead of
+ *         recomputing the transport; must not alias I_in or I_out; NULL to skip
  * Directions with |n_0| < n0_crit leave the step with zero intensity.
  */
 int rt_step(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
             const double *rho, const double *u_tet, const double *kappa_a,
-            const double *kappa_s, double dt, double *dT0, double *lum);
+            const double *kappa_s, double dt, double *dT0, double *lum, void *I_star);
 
 /*
  * Adjoint of rt_step for the functional J = sum over steps of
@@ -170,12 +174,15 @@ int rt_step(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
  *     work is caller-owned scratch of the same size, not aliasing the others
  *   T_n, lamT_np1, lamT_n (dev) [cells]; lamT_n may alias lamT_np1
  *   grad_kappa_a, grad_kappa_s (dev) [cells], accumulated (+=), or NULL
+ *   I_star (dev, optional, const) I* of this step as written by rt_step's
+ *     I_star output for the same inputs; when given, the transport is not
+ *     recomputed (the caller guarantees it matches I_n); NULL to recompute
  */
 int rt_step_adjoint(rt_grid *g, void *stream, const void *I_n, const double *T_n,
                     const double *rho, const double *u_tet, const double *kappa_a,
                     const double *kappa_s, double dt, double lum_weight, const void *lamI_np1,
                     const double *lamT_np1, void *lamI_n, double *lamT_n, void *work,
-                    double *grad_kappa_a, double *grad_kappa_s);
+                    double *grad_kappa_a, double *grad_kappa_s, const void *I_star);
 
 /*
  * Radiation moments per cell (Sec. 2.5):

@@ -5,7 +5,8 @@ luminosity face.  The forward pass runs the HIP step and keeps a checkpoint of
 (I, T) every K steps; the backward pass walks the segments newest first,
 recomputes the K states of a segment from its checkpoint, and applies the
 hand-written adjoint step (rt_step_adjoint) in reverse.  Memory is
-ceil(N/K) checkpoints + K segment states + three adjoint buffers.
+ceil(N/K) checkpoints + K segment states and K transport results (I*) +
+three adjoint buffers.
 
 Gradients are returned for the initial intensities, the initial gas
 temperature and the per-cell absorption and scattering opacities.
@@ -47,22 +48,25 @@ class RadTransport(torch.autograd.Function):
         work = torch.empty_like(I0)
         gka = torch.zeros_like(ka)
         gks = torch.zeros_like(ks)
+        # segment buffers: the K states, and I* of each step (the transport
+        # result the forward step hands to the coupling), so the adjoint
+        # step does not recompute the transport
+        nK = min(K, ctx.nsteps)
+        Ibuf = [torch.empty_like(I0) for _ in range(nK + 1)]
+        Sbuf = [torch.empty_like(I0) for _ in range(nK)]
+        Tbuf = [torch.empty_like(T0) for _ in range(nK)]
         nseg = len(ctx.ckpts)
         for seg in reversed(range(nseg)):
             s0 = seg * K
             s1 = min(ctx.nsteps, s0 + K)
-            I, T = ctx.ckpts[seg][0].clone(), ctx.ckpts[seg][1].clone()
-            Ib = torch.empty_like(I)
-            states = []
-            for _ in range(s0, s1):
-                states.append((I.clone(), T.clone()))
-                g.step(I, Ib, T, rho, u, ka, ks, dt)
-                I, Ib = Ib, I
-            for s in reversed(range(s0, s1)):
-                Is, Ts = states[s - s0]
-                g.step_adjoint(Is, Ts, rho, u, ka, ks, dt, lamI, lamT, lamI, lamT, work,
-                               gka, gks, lum_weight=w)
-            del states
+            Ibuf[0].copy_(ctx.ckpts[seg][0])
+            T = ctx.ckpts[seg][1].clone()
+            for j in range(s1 - s0):
+                Tbuf[j].copy_(T)
+                g.step(Ibuf[j], Ibuf[j + 1], T, rho, u, ka, ks, dt, I_star=Sbuf[j])
+            for j in reversed(range(s1 - s0)):
+                g.step_adjoint(Ibuf[j], Tbuf[j], rho, u, ka, ks, dt, lamI, lamT, lamI, lamT, work,
+                               gka, gks, lum_weight=w, I_star=Sbuf[j])
         ctx.ckpts = None
         return lamI, lamT, gka, gks, None, None, None, None, None, None
 

@@ -11,7 +11,8 @@
 //                  implicit-function theorem dT+/dB_k = -T+^k / P'(T+), the
 //                  FP64 angle sums by their own adjoint sums.  Writes
 //                  psi = (dJ/dI*) / (n^0 n_0) per cell-direction.
-//   k_adj_transport (one lane per cell-direction) gathers over the faces
+//   k_adj_transport (one lane per cell-direction; the tiled k_adj_march in
+//                  its place for spatially uniform geometry) gathers over the faces
 //                  whose upwind value depends on the cell (radius 2): the
 //                  direct term, the upwind PLM fluxes with the van Leer
 //                  limiter's Jacobian on the branch the forward took, the
@@ -33,7 +34,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     const double *__restrict__ rho, const double *__restrict__ uvec,
     const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt,
     const Real *__restrict__ lamI1, const double *__restrict__ lamT1, Real *__restrict__ psi,
-    double *__restrict__ lamT0, double *__restrict__ gka, double *__restrict__ gks) {
+    double *__restrict__ lamT0, double *__restrict__ gka, double *__restrict__ gks,
+    const Real *__restrict__ Istar) {
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     const long long ncell = (long long)G.n0 * G.n1 * G.n2;
@@ -53,26 +55,37 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + kWave * ch;
             Is[ch] = Real(0);
-            if (n < N) Is[ch] = transport_dir(G, Iin, x, n, dtR, ivol, dummy_l, dummy_m);
+            if (n >= N) continue;
+            // I* as stored by the forward step, or recomputed
+            Is[ch] = Istar ? Istar[x.c * N + n] : transport_dir(G, Iin, x, n, dtR, ivol, dummy_l, dummy_m);
         }
-        // forward coupling, recomputed
+        // forward coupling, recomputed.  Per direction: nb = n^0bar (fluid
+        // frame), dn = n^0 + nb (alpha_a + alpha_s) dt, rr = 1/(nb^2 dn);
+        // every quotient below is a product with rr
         const double u1 = uvec[3 * x.c], u2 = uvec[3 * x.c + 1], u3 = uvec[3 * x.c + 2];
         const double u0 = sqrt(1.0 + u1 * u1 + u2 * u2 + u3 * u3);
         const double rh = rho[x.c];
         const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh, aE = aa + as;
         const double n0 = G.n0u[x.gc];
+        double nbv[NCH], dnv[NCH], rrv[NCH], dom[NCH];
         double Em = 0.0, A1 = 0.0, A2 = 0.0;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + kWave * ch;
-            if (n >= N || G.mask[(size_t)x.gc * N + n]) continue;
-            const double nb = u0 - (u1 * G.nhat[3 * n] + u2 * G.nhat[3 * n + 1] + u3 * G.nhat[3 * n + 2]);
+            const bool live = n < N && !G.mask[(size_t)x.gc * N + (n < N ? n : 0)];
+            const int m = live ? n : 0;
+            const double nb = u0 - (u1 * G.nhat[3 * m] + u2 * G.nhat[3 * m + 1] + u3 * G.nhat[3 * m + 2]);
             const double dn = n0 + nb * aE * dt;
-            const double w = nb * nb * G.domega[n];
+            const double rr = rcp64(nb * nb * dn);
+            nbv[ch] = nb;
+            dnv[ch] = dn;
+            rrv[ch] = rr;
+            dom[ch] = live ? G.domega[m] : 0.0;   // zero weight: masked or padding
+            const double w = nb * nb * dom[ch];
             const double I = (double)Is[ch];
             Em += I * w;
-            A1 += (n0 / dn) * I * w;
-            A2 += G.domega[n] / (nb * dn);
+            A1 += (n0 * nb * nb * rr) * I * w;    // n^0/dn
+            A2 += dom[ch] * (nb * rr);            // dOmega/(nb dn)
         }
         Em = group_sum<kWave>(Em);
         A1 = group_sum<kWave>(A1);
@@ -90,21 +103,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         // adjoint sums over directions
         const bool beam_cell = G.beam != nullptr && G.beam[x.c];
         double lS = 0.0, X1 = 0.0, X2 = 0.0, X3 = 0.0;
+        double lpv[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + kWave * ch;
-            if (n >= N || G.mask[(size_t)x.gc * N + n]) continue;
-            const double nb = u0 - (u1 * G.nhat[3 * n] + u2 * G.nhat[3 * n + 1] + u3 * G.nhat[3 * n + 2]);
-            const double dn = n0 + nb * aE * dt;
-            const double k = n0 / dn;
-            const double gdir = dt / (kFourPi * dn * nb * nb * nb);
-            const double w = nb * nb * G.domega[n];
+            const double nb = nbv[ch], dn = dnv[ch], rr = rrv[ch];
+            const double k = n0 * nb * nb * rr;                    // n^0/dn
+            const double gdir = (dt / kFourPi) * nb * dn * rr * rr; // dt/(4 pi dn nb^3)
+            const double nbdn = nb * nb * nb * rr;                  // nb/dn
+            const double w = nb * nb * dom[ch];
             const double I = (double)Is[ch];
-            const double lp = (beam_cell && n == G.beam_angle) ? 0.0 : (double)lamI1[x.c * N + n];
+            const bool use = n < N && dom[ch] != 0.0 && !(beam_cell && n == G.beam_angle);
+            const double lp = use ? (double)lamI1[x.c * N + n] : 0.0;
+            lpv[ch] = lp;
+            const double idn = nb * nb * rr;                        // 1/dn
             lS += lp * gdir;
-            X1 += lp * (I * k + S * gdir) * nb / dn;
-            X2 += w * I * k * nb / dn;
-            X3 += G.domega[n] / (dn * dn);
+            X1 += lp * (I * k + S * gdir) * nbdn;
+            X2 += w * I * k * nbdn;
+            X3 += dom[ch] * idn * idn;
         }
         lS = group_sum<kWave>(lS);
         X1 = group_sum<kWave>(X1);
@@ -139,13 +155,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
             const int n = lane + kWave * ch;
             if (n >= N) continue;
             Real out = Real(0);
-            if (!G.mask[(size_t)x.gc * N + n]) {
-                const double nb = u0 - (u1 * G.nhat[3 * n] + u2 * G.nhat[3 * n + 1] + u3 * G.nhat[3 * n + 2]);
-                const double dn = n0 + nb * aE * dt;
-                const double k = n0 / dn;
-                const double w = nb * nb * G.domega[n];
-                const double lp = (beam_cell && n == G.beam_angle) ? 0.0 : (double)lamI1[x.c * N + n];
-                const double lstar = k * lp + (lEm + lA1 * k) * w;
+            if (dom[ch] != 0.0) {
+                const double nb = nbv[ch], rr = rrv[ch];
+                const double k = n0 * nb * nb * rr;
+                const double w = nb * nb * dom[ch];
+                const double lstar = k * lpv[ch] + (lEm + lA1 * k) * w;
                 out = Real(lstar / (double)q[(size_t)x.gc * N + n]);
             }
             psi[x.c * N + n] = out;
@@ -278,7 +292,8 @@ template <typename Real>
 int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
                  const double *rho, const double *u, const double *ka, const double *ks,
                  double dt, double lum_weight, const void *lamI1, const double *lamT1,
-                 void *lamI0, double *lamT0, void *work, double *gka, double *gks) {
+                 void *lamI0, double *lamT0, void *work, double *gka, double *gks,
+                 const void *Istar) {
     const DevGrid &G = g->dg;
     const long long ncell = (long long)G.n0 * G.n1 * G.n2;
     const int nblk = (int)((ncell + kCellsPerBlock - 1) / kCellsPerBlock);
@@ -289,7 +304,8 @@ int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
 #define RT_LAUNCH(NC)                                                                          \
     case NC:                                                                                   \
         hipLaunchKernelGGL((k_adj_couple<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in,   \
-                           Tin, rho, u, ka, ks, dt, l1, lamT1, psi, lamT0, gka, gks);          \
+                           Tin, rho, u, ka, ks, dt, l1, lamT1, psi, lamT0, gka, gks,           \
+                           static_cast<const Real *>(Istar));                                  \
         break;
     switch (nch) {
         RT_LAUNCH(1)
@@ -305,6 +321,7 @@ int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
     }
 #undef RT_LAUNCH
     if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
+    if (g->march.enabled) return launch_adj_march(g, s, Iin, psi, dt, lum_weight, lamI0);
 #define RT_LAUNCH2(NC)                                                                         \
     case NC:                                                                                   \
         hipLaunchKernelGGL((k_adj_transport<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in,    \
@@ -332,12 +349,13 @@ int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
 int launch_adjoint(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
                    const double *rho, const double *u, const double *ka, const double *ks,
                    double dt, double lum_weight, const void *lamI1, const double *lamT1,
-                   void *lamI0, double *lamT0, void *work, double *gka, double *gks) {
+                   void *lamI0, double *lamT0, void *work, double *gka, double *gks,
+                   const void *Istar) {
     if (g->precision == RT_F32)
         return launch_adj_t<float>(g, s, Iin, Tin, rho, u, ka, ks, dt, lum_weight, lamI1, lamT1,
-                                   lamI0, lamT0, work, gka, gks);
+                                   lamI0, lamT0, work, gka, gks, Istar);
     return launch_adj_t<double>(g, s, Iin, Tin, rho, u, ka, ks, dt, lum_weight, lamI1, lamT1,
-                                lamI0, lamT0, work, gka, gks);
+                                lamI0, lamT0, work, gka, gks, Istar);
 }
 
 }  // namespace rt

@@ -33,6 +33,13 @@ __device__ __forceinline__ double rcp64(double x) {
     return fma(r, e, r);
 }
 
+// 1/x in FP64 with one Newton step on the hardware estimate (the estimate's
+// error is squared, which suffices when it is below ~2^-26).
+__device__ __forceinline__ double rcp64_1(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Half of the van Leer (1974) harmonic-mean slope of the three values
 // (a, b, c) in index space: delta/2 = (b-a)(c-b)/((b-a)+(c-b)) when the two
 // differences share a sign, else 0 (Sec. 2.3, PLM).

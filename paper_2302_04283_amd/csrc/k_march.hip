@@ -14,7 +14,8 @@
 //     the current plane with a two-cell cross-shaped halo;
 //   * PLM is evaluated on the upwind side only (a face needs only I_L or I_R);
 //     each face value is computed by the same expression from the same inputs
-//     in both cells that share it, so face fluxes telescope exactly;
+//     in both cells that share it, so face fluxes telescope exactly; along
+//     axis 2 the upper face value of a plane is kept for the next plane;
 //   * workgroups are dispatched round-robin over the 8 XCDs; the logical tile
 //     order is remapped so that each XCD owns a contiguous band of tiles and
 //     halo rows hit its own L2.
@@ -23,27 +24,10 @@
 #include <cstdlib>
 
 #include "k_common.h"
+#include "k_tile.h"
 
 namespace rt {
 namespace {
-
-constexpr int kT = 4;            // tile edge
-constexpr int kTC = kT * kT;     // interior cells per tile
-constexpr int kHalo = 32;        // cross-shaped halo cells (2 deep)
-constexpr int kPlane = kTC + kHalo;
-
-// bits of the per-direction flag byte
-constexpr unsigned kXP = 1, kXN = 2, kYP = 4, kYN = 8, kZP = 16, kZN = 32, kMasked = 64;
-
-__device__ __forceinline__ int plane_slot(int x, int y) {
-    if (x >= 0 && x < kT && y >= 0 && y < kT) return y * kT + x;
-    if (y >= 0 && y < kT) return kTC + y * 4 + (x < 0 ? x + 2 : x - 2);
-    return kTC + 16 + (y < 0 ? y + 2 : y - 2) * 4 + x;
-}
-
-struct Seg {
-    int tx0, ty0, z0, z1;
-};
 
 #ifndef RT_MARCH_WAVES_PER_EU
 #define RT_MARCH_WAVES_PER_EU 2
@@ -55,10 +39,14 @@ void k_march(
     DevGrid G, MarchInfo M, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
     const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt,
-    double *__restrict__ dT0, double *__restrict__ partials, int *__restrict__ nr_partial) {
+    double *__restrict__ dT0, double *__restrict__ partials, int *__restrict__ nr_partial,
+    Real *__restrict__ Istar) {
     constexpr int NT = 16 * SW;
     constexpr int NW = NT / kWave;
     constexpr int NP = NC * SW;               // padded direction count
+    // FP32 planes are double-buffered (plane z+1 is written while plane z is
+    // read, one barrier per plane); FP64 planes do not fit twice in LDS
+    constexpr int NBUF = sizeof(Real) == 4 ? 2 : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double sh_l[NW], sh_m[NW];
     __shared__ int sh_n[NW];
@@ -93,8 +81,9 @@ void k_march(
     double *s_dom = s_nh + 3 * NP;                            // [NP] dOmega (0 if masked/pad)
     double *s_dom_all = s_dom + NP;                           // [NP] dOmega (0 if pad)
     Real *s_tab = reinterpret_cast<Real *>(s_dom_all + NP);   // [5][NP] q, 1/q, cx, cy, cz (signed)
-    Real *s_pl = s_tab + 5 * NP;                              // [kPlane][P]
-    unsigned char *s_bits = reinterpret_cast<unsigned char *>(s_pl + kPlane * M.pstride);  // [NP]
+    Real *s_pl = s_tab + 5 * NP;                              // [NBUF][kPlane][P]
+    unsigned char *s_bits =
+        reinterpret_cast<unsigned char *>(s_pl + NBUF * kPlane * M.pstride);   // [NP]
     const int P = M.pstride;
 
     for (int i = threadIdx.x; i < NP; i += NT) {
@@ -119,15 +108,7 @@ void k_march(
     if (threadIdx.x < kHalo) {
         const int h = threadIdx.x;
         int x, y;
-        if (h < 16) {
-            y = h / 4;
-            const int hx = h % 4;
-            x = hx < 2 ? hx - 2 : hx + 2;
-        } else {
-            const int hy = (h - 16) / 4;
-            x = (h - 16) % 4;
-            y = hy < 2 ? hy - 2 : hy + 2;
-        }
+        halo_pos(h, x, y);
         int gx = sg.tx0 + x, gy = sg.ty0 + y;
         unsigned test = 0;
         if (gx < 0 || gx >= G.n0) {
@@ -176,6 +157,10 @@ void k_march(
     const bool on_lum_xy = (G.lum_axis == 0 && gx == (lside ? G.n0 - 1 : 0)) ||
                            (G.lum_axis == 1 && gy == (lside ? G.n1 - 1 : 0));
 
+    // every boundary periodic: no ghost ever needs the outflow test
+    const bool all_periodic = G.bc[0][0] == RT_BC_PERIODIC && G.bc[0][1] == RT_BC_PERIODIC &&
+                              G.bc[1][0] == RT_BC_PERIODIC && G.bc[1][1] == RT_BC_PERIODIC &&
+                              G.bc[2][0] == RT_BC_PERIODIC && G.bc[2][1] == RT_BC_PERIODIC;
     // plane pz of a row, with the axis-2 boundary condition; `xytest` is the
     // axis-0/1 outflow test of a halo row (0: always copy)
     auto load_row = [&](int pz, long long r, unsigned xytest, Real *dst) {
@@ -191,10 +176,15 @@ void k_march(
             }
         }
         const Real *src = Iin + (zz * pcells + r) * N;
+        if (all_periodic) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) dst[k] = src[k < NC - 1 ? a + SW * k : min(a + SW * k, N - 1)];
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int n = a + SW * k;
-            const Real v = src[min(n, N - 1)];
+            const Real v = src[k < NC - 1 ? n : min(n, N - 1)];
             // ghost of an outflow/vacuum boundary: copy for directions leaving
             // through it (all bits of `test` set; test = 0 always copies)
             dst[k] = ((s_bits[n] & test) == test) ? v : Real(0);
@@ -210,31 +200,60 @@ void k_march(
                      : (f == 3 ? rho[c] : (f == 4 ? kap_a[c] : (f == 5 ? kap_s[c] : T[c])));
     };
 
-    Real qz[5][NC], hal[2][NC];
+    // first plane of the segment into LDS: own cell from the queue, two halo
+    // cells per lane group; later planes are written at the end of a step
+    Real qz[5][NC];
 #pragma unroll
     for (int p = 0; p < 5; ++p) load_row(sg.z0 - 2 + p, row, 0u, qz[p]);
-    load_row(sg.z0, hrow0, htest0, hal[0]);
-    load_row(sg.z0, hrow1, htest1, hal[1]);
-    double flv = load_fluid(sg.z0);
+    {
+        Real h0[NC], h1[NC];
+        load_row(sg.z0, hrow0, htest0, h0);
+        load_row(sg.z0, hrow1, htest1, h1);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int n = a + SW * k;
+            s_pl[o_c + n] = qz[2][k];
+            s_pl[(kTC + 2 * cl) * P + n] = h0[k];
+            s_pl[(kTC + 2 * cl + 1) * P + n] = h1[k];
+        }
+        const double flv = load_fluid(sg.z0);
+        if (a < 7) s_fl[cl][a] = flv;
+    }
+    // Axis-2 face value carried from plane to plane.  The upper face of plane
+    // z is the lower face of plane z+1, and both cells form its value with
+    // the same expression from the same inputs, so it is formed once; the
+    // lower face of the segment's first plane is formed here from the queue.
+    Real zc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const bool nz = (s_bits[a + SW * k] & kZN) != 0;
+        const Real l = nz ? qz[3][k] : qz[0][k];
+        const Real m = nz ? qz[2][k] : qz[1][k];
+        const Real r = nz ? qz[1][k] : qz[2][k];
+        zc[k] = plm ? m + half_slope(l, m, r) : m;
+    }
+
+    // per-lane direction flags (loop invariant): motion along -axis 0/1/2, masked
+    bool fx[NC], fy[NC], fz[NC], fm[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const unsigned b = s_bits[a + SW * k];
+        fx[k] = (b & kXN) != 0;
+        fy[k] = (b & kYN) != 0;
+        fz[k] = (b & kZN) != 0;
+        fm[k] = (b & kMasked) != 0;
+    }
 
     double lum_acc = 0.0, me_acc = 0.0;
     int nr_acc = 0;
 
     for (int z = sg.z0; z < sg.z1; ++z) {
-        // current plane into LDS: own cell from the queue, two halo cells
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int n = a + SW * k;
-            s_pl[o_c + n] = qz[2][k];
-            s_pl[(kTC + 2 * cl) * P + n] = hal[0][k];
-            s_pl[(kTC + 2 * cl + 1) * P + n] = hal[1][k];
-        }
-        if (a < 7) s_fl[cl][a] = flv;
+        const Real *pl = s_pl + (NBUF == 2 ? ((z - sg.z0) & 1) : 0) * kPlane * P;
         __syncthreads();
         // prefetch the next plane while this one is computed
         const bool more = z + 1 < sg.z1;
         Real qn[NC], hn[2][NC];
-        double fln = flv;
+        double fln = 0.0;
         if (more) {
             load_row(z + 3, row, 0u, qn);
             load_row(z + 1, hrow0, htest0, hn[0]);
@@ -250,53 +269,54 @@ void k_march(
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int n = a + SW * k;
-            const unsigned bits = s_bits[n];
             const Real Ic = qz[2][k];
             // upwind-ordered neighbours; a direction without motion along an
             // axis has a zero coefficient there, so its branch is irrelevant
-            const bool nx = (bits & kXN) != 0, ny = (bits & kYN) != 0, nz = (bits & kZN) != 0;
+            const bool nx = fx[k], ny = fy[k], nz = fz[k];
             // all four axis-0/1 neighbours at fixed offsets, then the upwind order
-            const Real xm2 = s_pl[ox[0] + n], xm1 = s_pl[ox[1] + n];
-            const Real xp1 = s_pl[ox[2] + n], xp2 = s_pl[ox[3] + n];
-            const Real ym2 = s_pl[oy[0] + n], ym1 = s_pl[oy[1] + n];
-            const Real yp1 = s_pl[oy[2] + n], yp2 = s_pl[oy[3] + n];
+            const Real xm2 = pl[ox[0] + n], xm1 = pl[ox[1] + n];
+            const Real xp1 = pl[ox[2] + n], xp2 = pl[ox[3] + n];
+            const Real ym2 = pl[oy[0] + n], ym1 = pl[oy[1] + n];
+            const Real yp1 = pl[oy[2] + n], yp2 = pl[oy[3] + n];
             const Real x0 = nx ? xp2 : xm2, x1 = nx ? xp1 : xm1, x3 = nx ? xm1 : xp1;
             const Real y0 = ny ? yp2 : ym2, y1 = ny ? yp1 : ym1, y3 = ny ? ym1 : yp1;
-            const Real z0 = nz ? qz[4][k] : qz[0][k];
-            const Real z1 = nz ? qz[3][k] : qz[1][k];
-            const Real z3 = nz ? qz[1][k] : qz[3][k];
-            Real Iax, Ibx, Iay, Iby, Iaz, Ibz;
+            // upper axis-2 face: the outflow face for motion along +axis 2
+            // (upwind cell z), the inflow face otherwise (upwind cell z+1)
+            const Real zl = nz ? qz[4][k] : qz[1][k];
+            const Real zm = nz ? qz[3][k] : qz[2][k];
+            const Real zr = nz ? qz[2][k] : qz[3][k];
+            Real Iax, Ibx, Iay, Iby, zup;
             if (plm) {
                 Iax = x1 + half_slope(x0, x1, Ic);
                 Ibx = Ic + half_slope(x1, Ic, x3);
                 Iay = y1 + half_slope(y0, y1, Ic);
                 Iby = Ic + half_slope(y1, Ic, y3);
-                Iaz = z1 + half_slope(z0, z1, Ic);
-                Ibz = Ic + half_slope(z1, Ic, z3);
+                zup = zm + half_slope(zl, zm, zr);
             } else {
                 Iax = x1;
                 Ibx = Ic;
                 Iay = y1;
                 Iby = Ic;
-                Iaz = z1;
-                Ibz = Ic;
+                zup = zm;
             }
+            // inflow (a) and outflow (b) face values along axis 2
+            const Real Iaz = nz ? zup : zc[k];
+            const Real Ibz = nz ? zc[k] : zup;
+            zc[k] = zup;
             // signed coefficients: +-C/dV with the sign of the motion
             const Real cx = s_tab[2 * NP + n], cy = s_tab[3 * NP + n], cz = s_tab[4 * NP + n];
-            const Real Fax = cx * Iax, Fbx = cx * Ibx;
-            const Real Fay = cy * Iay, Fby = cy * Iby;
-            const Real Faz = cz * Iaz, Fbz = cz * Ibz;
-            const Real dq = ((Fbx - Fax) + (Fby - Fay)) + (Fbz - Faz);
-            const Real Qs = s_tab[n] * Ic - dtR * dq;
+            const Real dq = fma(cz, Ibz - Iaz, fma(cy, Iby - Iay, cx * (Ibx - Iax)));
+            const Real Qs = fma(-dtR, dq, s_tab[n] * Ic);
             if constexpr (sizeof(Real) == 4)
                 Is[k] = Qs * s_tab[NP + n];
             else
                 Is[k] = Qs / s_tab[n];
             if (M.any_mask) {
-                const bool msk = (bits & kMasked) != 0;
+                const bool msk = fm[k];
                 me_acc -= msk ? vol * s_dom_all[n] * (double)Qs : 0.0;
                 Is[k] = msk ? Real(0) : Is[k];
             }
+            if (Istar && (k < NC - 1 || n < N)) Istar[cidx * N + n] = Is[k];
             if (lum_wave) {
                 // energy leaving through the face.  With the signed
                 // coefficients, the face's flux (dA n^a n_0 I_up)/dV is Fb when
@@ -304,9 +324,9 @@ void k_march(
                 // inflow side; the outward orientation of a lower face adds a
                 // minus sign
                 double F = 0.0;
-                if (G.lum_axis == 0) F = (double)(nx == (lside == 0) ? Fbx : -Fax);
-                else if (G.lum_axis == 1) F = (double)(ny == (lside == 0) ? Fby : -Fay);
-                else F = (double)(nz == (lside == 0) ? Fbz : -Faz);
+                if (G.lum_axis == 0) F = (double)(nx == (lside == 0) ? cx * Ibx : -(cx * Iax));
+                else if (G.lum_axis == 1) F = (double)(ny == (lside == 0) ? cy * Iby : -(cy * Iay));
+                else F = (double)(nz == (lside == 0) ? cz * Ibz : -(cz * Iaz));
                 lum_acc -= lum_here ? s_dom_all[n] * vol * F : 0.0;
             }
         }
@@ -323,15 +343,16 @@ void k_march(
         for (int k = 0; k < NC; ++k) {
             const int n = a + SW * k;
             const double dom = s_dom[n];
-            const double nb = u0 - (u1 * s_nh[n] + u2 * s_nh[NP + n] + u3 * s_nh[2 * NP + n]);
-            const double dn = n0u + nb * tau;
-            const double r = rcp64(nb * nb * dn);      // 1/(nb^2 dn)
+            const double nb = u0 - fma(u1, s_nh[n], fma(u2, s_nh[NP + n], u3 * s_nh[2 * NP + n]));
+            const double dn = fma(nb, tau, n0u);
+            // 1/(nb^2 dn); one Newton step suffices for FP32 intensities
+            const double r = sizeof(Real) == 4 ? rcp64_1(nb * nb * dn) : rcp64(nb * nb * dn);
             const double r1 = nb * r;                  // 1/(nb dn)
             const double kn = n0u * nb * r1;           // n^0/dn
             const double Iw = (double)Is[k] * (nb * nb * dom);
             Em += Iw;
-            A1 += kn * Iw;
-            A2 += dom * r1;
+            A1 = fma(kn, Iw, A1);
+            A2 = fma(dom, r1, A2);
             kk[k] = Real(kn);
             gg[k] = Real(nb * dn * r * r);             // 1/(dn nb^3)
         }
@@ -353,13 +374,13 @@ void k_march(
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int n = a + SW * k;
-            const Real Ip = kk[k] * Is[k] + cS * gg[k];
+            const Real Ip = fma(kk[k], Is[k], cS * gg[k]);
             const double dI = (double)(Ip - Is[k]) * s_dom[n];
             Mv0 += dI;
-            Mv1 += dI * s_nh[n];
-            Mv2 += dI * s_nh[NP + n];
-            Mv3 += dI * s_nh[2 * NP + n];
-            Real out = (s_bits[n] & kMasked) ? Real(0) : Ip;
+            Mv1 = fma(dI, s_nh[n], Mv1);
+            Mv2 = fma(dI, s_nh[NP + n], Mv2);
+            Mv3 = fma(dI, s_nh[2 * NP + n], Mv3);
+            Real out = fm[k] ? Real(0) : Ip;
             out = (beam_cell && n == G.beam_angle) ? Real(G.beam_I) : out;
             if (k < NC - 1 || n < N) dst[n] = out;
         }
@@ -377,19 +398,27 @@ void k_march(
                                                  E0[4 * al + 2] * Mv2 + E0[4 * al + 3] * Mv3);
             }
         }
-        __syncthreads();
+        // single buffer: every group must be done reading plane z first.
+        // Double buffer: the other buffer held plane z-1, whose readers have
+        // all passed this iteration's first barrier.  The fluid slot of a
+        // cell is read only by its own lane group, which wrote it.
+        if constexpr (NBUF == 1) __syncthreads();
         if (more) {
+            Real *nx = s_pl + (NBUF == 2 ? ((z + 1 - sg.z0) & 1) : 0) * kPlane * P;
+            // next plane into LDS straight from the queue and prefetch registers
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
+                const int n = a + SW * k;
+                nx[o_c + n] = qz[3][k];
+                nx[(kTC + 2 * cl) * P + n] = hn[0][k];
+                nx[(kTC + 2 * cl + 1) * P + n] = hn[1][k];
                 qz[0][k] = qz[1][k];
                 qz[1][k] = qz[2][k];
                 qz[2][k] = qz[3][k];
                 qz[3][k] = qz[4][k];
                 qz[4][k] = qn[k];
-                hal[0][k] = hn[0][k];
-                hal[1][k] = hn[1][k];
             }
-            flv = fln;
+            if (a < 7) s_fl[cl][a] = fln;
         }
     }
 
@@ -421,7 +450,7 @@ void k_march(
 template <typename Real, int SW, int NC>
 int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                const double *rho, const double *u, const double *ka, const double *ks,
-               double dt, double *dT0) {
+               double dt, double *dT0, Real *Istar) {
     const MarchInfo &M = g->march;
     static bool lds_set = false;   // one attribute call per instantiation
     if (!lds_set) {
@@ -433,7 +462,7 @@ int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T
     }
     hipLaunchKernelGGL((k_march<Real, SW, NC>), dim3(M.grid), dim3(16 * SW), M.lds, s, g->dg, M,
                        static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho, u, ka,
-                       ks, dt, dT0, g->partials, g->noroot_partial);
+                       ks, dt, dT0, g->partials, g->noroot_partial, Istar);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
 }
 
@@ -478,17 +507,19 @@ int march_pstride(int precision, int nang) {
 
 size_t march_lds_bytes(int precision, int nang, int np) {
     const size_t real = precision == RT_F32 ? 4 : 8;
+    const size_t nbuf = precision == RT_F32 ? 2 : 1;   // as NBUF in k_march
     return (size_t)np * (5 * 8 + 5 * real + 1) +
-           (size_t)kPlane * march_pstride(precision, np) * real;
+           nbuf * kPlane * march_pstride(precision, np) * real;
 }
 
 int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                  const double *rho, const double *u, const double *ka, const double *ks,
-                 double dt, double *dT0) {
+                 double dt, double *dT0, void *Istar) {
     const MarchInfo &M = g->march;
 #define RT_CASE(R, SW, NC)                                                                    \
     if (M.sw == SW && M.nc == NC)                                                             \
-        return launch_one<R, SW, NC>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0);
+        return launch_one<R, SW, NC>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0,          \
+                                     static_cast<R *>(Istar));
     if (g->precision == RT_F32) {
         RT_CASE(float, 16, 1)
         RT_CASE(float, 16, 3)

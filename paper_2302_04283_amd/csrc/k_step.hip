@@ -31,7 +31,8 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                                                  const double *__restrict__ kap_s, double dt,
                                                  double *__restrict__ dT0,
                                                  double *__restrict__ partials,
-                                                 int *__restrict__ nr_partial) {
+                                                 int *__restrict__ nr_partial,
+                                                 Real *__restrict__ Istar) {
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     const long long ncell = (long long)G.n0 * G.n1 * G.n2;
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
             Is[ch] = Real(0);
             if (n >= N) continue;
             Is[ch] = transport_dir(G, Iin, x, n, dtR, ivol, lum_acc, me_acc);
+            if (Istar) Istar[x.c * N + n] = Is[ch];
         }
 
         // ---------------------------------------------------------- coupling
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(DevGrid G, const Real *__res
 template <typename Real>
 int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                   const double *rho, const double *u, const double *ka, const double *ks,
-                  double dt, double *dT0, double *lum) {
+                  double dt, double *dT0, double *lum, void *Istar) {
     const DevGrid &G = g->dg;
     const int nblk = step_blocks(g);
     const int nch = (G.nang + kWave - 1) / kWave;
@@ -251,7 +253,8 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
 #define RT_LAUNCH(NC)                                                                          \
     case NC:                                                                                   \
         hipLaunchKernelGGL((k_step<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in, out, T, \
-                           rho, u, ka, ks, dt, dT0, g->partials, g->noroot_partial);          \
+                           rho, u, ka, ks, dt, dT0, g->partials, g->noroot_partial,           \
+                           static_cast<Real *>(Istar));                                        \
         break;
     switch (nch) {
         RT_LAUNCH(1)
@@ -285,15 +288,15 @@ int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *l
 
 int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                 const double *rho, const double *u, const double *ka, const double *ks,
-                double dt, double *dT0, double *lum) {
+                double dt, double *dT0, double *lum, void *Istar) {
     if (g->march.enabled) {
-        int rc = launch_march(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0);
+        int rc = launch_march(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar);
         if (rc != RT_OK) return rc;
         return launch_finalize(g, s, g->march.grid, dt, lum);
     }
     if (g->precision == RT_F32)
-        return launch_step_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
-    return launch_step_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+        return launch_step_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, Istar);
+    return launch_step_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, Istar);
 }
 
 int launch_moments(rt_grid *g, hipStream_t s, const void *I, const double *u, double *R,

@@ -361,17 +361,19 @@ int rt_max_dt(const rt_grid *g, double cfl, double *dt) {
 
 int rt_step(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
             const double *rho, const double *u_tet, const double *kappa_a,
-            const double *kappa_s, double dt, double *dT0, double *lum) {
+            const double *kappa_s, double dt, double *dT0, double *lum, void *I_star) {
     if (!g) return fail(RT_EINVAL, "grid is NULL");
     if (!I_in || !I_out || !T || !rho || !u_tet || !kappa_a || !kappa_s)
         return fail(RT_EINVAL, "NULL state pointer");
     if (I_in == I_out) return fail(RT_EINVAL, "I_out must not alias I_in");
+    if (I_star && (I_star == I_in || I_star == I_out))
+        return fail(RT_EINVAL, "I_star must not alias I_in or I_out");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RT_EINVAL, "dt must be positive and finite");
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != g->device) (void)hipSetDevice(g->device);
     int rc = rt::launch_step(g, (hipStream_t)stream, I_in, I_out, T, rho, u_tet, kappa_a, kappa_s,
-                             dt, dT0, lum);
+                             dt, dT0, lum, I_star);
     if (cur != g->device) (void)hipSetDevice(cur);
     if (rc != RT_OK) return fail(rc, "kernel launch failed");
     return RT_OK;
@@ -381,13 +383,15 @@ int rt_step_adjoint(rt_grid *g, void *stream, const void *I_n, const double *T_n
                     const double *rho, const double *u_tet, const double *kappa_a,
                     const double *kappa_s, double dt, double lum_weight, const void *lamI_np1,
                     const double *lamT_np1, void *lamI_n, double *lamT_n, void *work,
-                    double *grad_kappa_a, double *grad_kappa_s) {
+                    double *grad_kappa_a, double *grad_kappa_s, const void *I_star) {
     if (!g) return fail(RT_EINVAL, "grid is NULL");
     if (!I_n || !T_n || !rho || !u_tet || !kappa_a || !kappa_s || !lamI_np1 || !lamT_np1 ||
         !lamI_n || !lamT_n || !work)
         return fail(RT_EINVAL, "NULL state pointer");
     if (work == I_n || work == lamI_np1 || work == lamI_n || lamI_n == I_n)
         return fail(RT_EINVAL, "work must not alias the state or the adjoint buffers");
+    if (I_star && (I_star == work || I_star == lamI_n))
+        return fail(RT_EINVAL, "I_star must not alias work or lamI_n");
     if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(lum_weight))
         return fail(RT_EINVAL, "dt must be positive and finite");
     int cur = 0;
@@ -395,7 +399,7 @@ int rt_step_adjoint(rt_grid *g, void *stream, const void *I_n, const double *T_n
     if (cur != g->device) (void)hipSetDevice(g->device);
     int rc = rt::launch_adjoint(g, (hipStream_t)stream, I_n, T_n, rho, u_tet, kappa_a, kappa_s, dt,
                                 lum_weight, lamI_np1, lamT_np1, lamI_n, lamT_n, work, grad_kappa_a,
-                                grad_kappa_s);
+                                grad_kappa_s, I_star);
     if (cur != g->device) (void)hipSetDevice(cur);
     if (rc != RT_OK) return fail(rc, "kernel launch failed");
     return RT_OK;

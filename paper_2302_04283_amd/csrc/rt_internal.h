@@ -120,7 +120,7 @@ struct rt_grid {
 namespace rt {
 int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                 const double *rho, const double *u, const double *ka, const double *ks,
-                double dt, double *dT0, double *lum);
+                double dt, double *dT0, double *lum, void *Istar);
 int launch_moments(rt_grid *g, hipStream_t s, const void *I, const double *u,
                    double *R, double *R0, double *E);
 int step_blocks(const rt_grid *g);
@@ -129,10 +129,13 @@ size_t march_lds_bytes(int precision, int nang, int np);
 int march_pstride(int precision, int nang);
 int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                  const double *rho, const double *u, const double *ka, const double *ks,
-                 double dt, double *dT0);
+                 double dt, double *dT0, void *Istar);
 int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *lum);
 int launch_adjoint(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
                    const double *rho, const double *u, const double *ka, const double *ks,
                    double dt, double lum_weight, const void *lamI1, const double *lamT1,
-                   void *lamI0, double *lamT0, void *work, double *gka, double *gks);
+                   void *lamI0, double *lamT0, void *work, double *gka, double *gks,
+                   const void *Istar);
+int launch_adj_march(rt_grid *g, hipStream_t s, const void *Iin, const void *psi, double dt,
+                     double lum_weight, void *lamI0);
 }  // namespace rt

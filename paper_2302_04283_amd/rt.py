@@ -74,10 +74,10 @@ def load():
                                  C.POINTER(C.c_int32)]
     lib.rt_angles.argtypes = [vp, _dp, _dp]
     lib.rt_max_dt.argtypes = [vp, C.c_double, _dp]
-    lib.rt_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
+    lib.rt_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp, vp]
     lib.rt_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.rt_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double,
-                                    vp, vp, vp, vp, vp, vp, vp]
+                                    vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rt_stats.argtypes = [vp, C.POINTER(C.c_int64), _dp]
     lib.rt_free.argtypes = [vp]
     lib.rt_free.restype = None
@@ -218,7 +218,7 @@ class Grid:
 
     # -------------------------------------------------------------- compute
     def step(self, I_in, I_out, T, rho, u, kappa_a, kappa_s, dt, dT0=None, lum=None,
-             stream=None):
+             stream=None, I_star=None):
         import torch
         rd = self.real_dtype()
         f8 = torch.float64
@@ -231,20 +231,23 @@ class Grid:
         self._need(kappa_s, self._cell_shape(), f8, "kappa_s")
         self._need(dT0, self._cell_shape(4), f8, "dT0")
         self._need(lum, (1,), f8, "lum")
+        self._need(I_star, self._state_shape(), rd, "I_star")
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         _check(self._lib.rt_step(self._h, C.c_void_p(s.cuda_stream), _dev(I_in), _dev(I_out),
                                  _dev(T), _dev(rho), _dev(u), _dev(kappa_a), _dev(kappa_s),
-                                 float(dt), _dev(dT0), _dev(lum)))
+                                 float(dt), _dev(dT0), _dev(lum), _dev(I_star)))
 
     def step_adjoint(self, I_n, T_n, rho, u, kappa_a, kappa_s, dt, lamI_next, lamT_next,
                      lamI_out, lamT_out, work, grad_kappa_a=None, grad_kappa_s=None,
-                     lum_weight=1.0, stream=None):
-        """Reverse of step() for J = sum dt * luminosity; see rt_step_adjoint."""
+                     lum_weight=1.0, stream=None, I_star=None):
+        """Reverse of step() for J = sum dt * luminosity; see rt_step_adjoint.
+        I_star: the I* that step(..., I_star=) wrote for the same inputs, or
+        None to recompute the transport."""
         import torch
         rd = self.real_dtype()
         f8 = torch.float64
         for t, name in ((I_n, "I_n"), (lamI_next, "lamI_next"), (lamI_out, "lamI_out"),
-                        (work, "work")):
+                        (work, "work"), (I_star, "I_star")):
             self._need(t, self._state_shape(), rd, name)
         for t, name in ((T_n, "T_n"), (rho, "rho"), (kappa_a, "kappa_a"), (kappa_s, "kappa_s"),
                         (lamT_next, "lamT_next"), (lamT_out, "lamT_out"),
@@ -256,7 +259,7 @@ class Grid:
             self._h, C.c_void_p(s.cuda_stream), _dev(I_n), _dev(T_n), _dev(rho), _dev(u),
             _dev(kappa_a), _dev(kappa_s), float(dt), float(lum_weight), _dev(lamI_next),
             _dev(lamT_next), _dev(lamI_out), _dev(lamT_out), _dev(work), _dev(grad_kappa_a),
-            _dev(grad_kappa_s)))
+            _dev(grad_kappa_s), _dev(I_star)))
 
     def moments(self, I, u=None, stream=None):
         import torch

@@ -135,3 +135,128 @@ def test_adjoint_full_c4_central_differences():
     print("[adjoint] c4 full 64x32x64x92 50 steps K=10: worst FD rel err %.2e "
           "(central differences, h = 1e-6 relative)" % worst, flush=True)
     g.close()
+
+
+# ------------------------------------------------------- stored I*, tiled adjoint
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("case", ["fast", "general"])
+def test_step_I_star_output_matches_oracle_transport(case, prec):
+    """rt_step's optional I* output is the oracle's transport result (before
+    the coupling), masked directions zero."""
+    if case == "fast":
+        p = W.make_problem("c2", scale=(8, 12, 5), nlev=3)
+    else:
+        p = W.make_problem("c4", scale=(12, 8, 6))
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    I0 = p.initial_intensity()
+    ref, _ = O.transport(torch.as_tensor(I0), S, dt)
+    ref = ref.numpy()
+    g = rt.Grid(p, prec)
+    assert g.fast_path == (case == "fast")
+    rd = g.real_dtype()
+    I = _t(I0).to(rd)
+    Ib = torch.empty_like(I)
+    Is = torch.full_like(I, float("nan"))
+    g.step(I, Ib, _t(p.T), _t(p.rho), _t(p.u_tet), _t(p.kappa_a), _t(p.kappa_s), dt,
+           I_star=Is)
+    got = Is.double().cpu().numpy()
+    g.close()
+    scale = np.abs(ref) + 1e-3 * np.abs(ref).max()
+    e = float(np.max(np.abs(got - ref) / scale))
+    print("[adjoint] I* output %s %s e=%.2e" % (case, "fp64" if prec == 0 else "fp32", e),
+          flush=True)
+    assert np.isfinite(got).all()
+    assert e <= (1e-12 if prec == rt.RT_F64 else 1e-5)
+
+
+def _tiled_problem(bc, lum_axis, lum_side, shape=(8, 8, 7), nlev=3, seed=5):
+    p = W.make_custom("minkowski_cart", shape, [(0.0, 1.0)] * 3, nlev, bc)
+    rng = np.random.default_rng(seed)
+    shp = p.T.shape
+    p.T[:] = 0.5 + rng.random(shp)
+    p.kappa_a[:] = 4.0 * rng.random(shp)
+    p.kappa_s[:] = 4.0 * rng.random(shp)
+    p.rho[:] = 0.5 + rng.random(shp)
+    p.u_tet[:] = 0.3 * (rng.random(shp + (3,)) - 0.5)
+    p.lum_axis, p.lum_side = lum_axis, lum_side
+    return p
+
+
+PER = [(0, 0)] * 3
+OUT = [(1, 1)] * 3
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("bc,lum_axis,lum_side", [
+    (PER, 0, 1), (PER, 1, 0), (PER, 2, 1), (PER, 2, 0),
+    (OUT, 0, 0), (OUT, 1, 1), (OUT, 2, 0), (OUT, 2, 1),
+    ([(0, 0), (1, 1), (0, 0)], 1, 0)])
+def test_tiled_adjoint_boundaries_and_luminosity_faces(bc, lum_axis, lum_side, prec):
+    """The tiled transport adjoint (uniform geometry) against the oracle's
+    reference gradient for every luminosity face and both boundary kinds."""
+    p = _tiled_problem(bc, lum_axis, lum_side)
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    steps = 4
+    I0 = np.abs(p.initial_intensity()) + 0.1
+    ref = GR.reference_gradient(p, I0, p.T, dt, steps)
+    g = rt.Grid(p, prec)
+    assert g.fast_path
+    g.close()
+    got = _gpu_grads(p, prec, steps, dt, 2, I0=I0)
+    tol = 1e-10 if prec == rt.RT_F64 else 1e-4
+    errs = {k: _max_rel(got[k], ref[k]) for k in ("kappa_a", "kappa_s", "T0", "I0")}
+    print("[adjoint] tiled bc=%s lum=(%d,%d) %s %s" % (
+        "per" if bc == PER else ("out" if bc == OUT else "mixed"), lum_axis, lum_side,
+        "fp64" if prec == 0 else "fp32", " ".join("e_%s=%.2e" % kv for kv in errs.items())),
+        flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
+@pytest.mark.parametrize("nlev,shape,seglen", [(4, (8, 4, 7), "3"), (2, (4, 8, 5), "2"),
+                                               (1, (4, 4, 3), "1"), (3, (4, 4, 6), "4")])
+def test_tiled_adjoint_matches_general_adjoint(monkeypatch, nlev, shape, seglen):
+    """Tiled and general adjoint on the same inputs (FP64): direction chunks
+    (162 directions span two chunks of 96, 92 one padded chunk), ragged
+    segments along axis 2."""
+    p = W.make_problem("c2", scale=shape, nlev=nlev)
+    dt = O.max_dt(O.setup(p), 0.3)
+    monkeypatch.setenv("RT_MARCH_SEGLEN", seglen)
+    g = rt.Grid(p, rt.RT_F64)
+    assert g.fast_path
+    g.close()
+    a = _gpu_grads(p, rt.RT_F64, 3, dt, 3)
+    monkeypatch.setenv("RT_MARCH", "0")
+    b = _gpu_grads(p, rt.RT_F64, 3, dt, 3)
+    errs = {k: _max_rel(a[k], b[k]) for k in ("kappa_a", "kappa_s", "T0", "I0")}
+    print("[adjoint] tiled vs general lev%d %s seglen %s %s" % (
+        nlev, shape, seglen, " ".join("e_%s=%.2e" % kv for kv in errs.items())), flush=True)
+    for k, e in errs.items():
+        assert e <= 1e-12, (k, e)
+
+
+def test_adjoint_with_and_without_stored_I_star():
+    """rt_step_adjoint given I* equals the adjoint that recomputes it."""
+    p = W.make_problem("c4", scale=(12, 8, 6))
+    dt = O.max_dt(O.setup(p), 0.3)
+    g = rt.Grid(p, rt.RT_F64)
+    I0 = _t(p.initial_intensity())
+    T0, rho, u, ka, ks = _t(p.T), _t(p.rho), _t(p.u_tet), _t(p.kappa_a), _t(p.kappa_s)
+    I1, Is = torch.empty_like(I0), torch.empty_like(I0)
+    T1 = T0.clone()
+    g.step(I0, I1, T1, rho, u, ka, ks, dt, I_star=Is)
+    rng = np.random.default_rng(11)
+    lamI1 = _t(rng.standard_normal(tuple(I0.shape)))
+    lamT1 = _t(rng.standard_normal(tuple(T0.shape)))
+    outs = []
+    for star in (None, Is):
+        lI, lT, work = torch.empty_like(I0), torch.empty_like(T0), torch.empty_like(I0)
+        gka, gks = torch.zeros_like(T0), torch.zeros_like(T0)
+        g.step_adjoint(I0, T0, rho, u, ka, ks, dt, lamI1, lamT1, lI, lT, work, gka, gks,
+                       lum_weight=0.7, I_star=star)
+        outs.append([x.cpu().numpy() for x in (lI, lT, gka, gks)])
+    g.close()
+    for x, y in zip(*outs):
+        assert _max_rel(x, y) <= 1e-13

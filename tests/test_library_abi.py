@@ -34,7 +34,9 @@ def test_host_error_paths():
     assert b"NULL" in lib.rt_last_error()
     assert lib.rt_geodesic_angles(0, None, None) == rt.RT_EINVAL
     assert lib.rt_step(None, None, None, None, None, None, None, None, None, 0.1, None,
-                       None) == rt.RT_EINVAL
+                       None, None) == rt.RT_EINVAL
+    assert lib.rt_step_adjoint(None, None, None, None, None, None, None, None, 0.1, 1.0,
+                               None, None, None, None, None, None, None, None) == rt.RT_EINVAL
     dt = C.c_double()
     assert lib.rt_max_dt(None, 0.3, C.byref(dt)) == rt.RT_EINVAL
     lib.rt_free(None)
