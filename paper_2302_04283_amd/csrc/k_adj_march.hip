@@ -70,12 +70,12 @@ __device__ __forceinline__ bool lum_face(int F, int len, bool periodic, int side
 }
 
 template <typename Real, int SW, int NC>
-__global__ __launch_bounds__(16 * SW) void k_adj_march(DevGrid G, MarchInfo M, int nchunk, int P,
+__global__ __launch_bounds__(kTC * SW) void k_adj_march(DevGrid G, MarchInfo M, int nchunk, int P,
                                                         const Real *__restrict__ Iin,
                                                         const Real *__restrict__ psi, double dt,
                                                         double lum_weight,
                                                         Real *__restrict__ lam) {
-    constexpr int NT = 16 * SW;
+    constexpr int NT = kTC * SW;
     constexpr int NP = NC * SW;   // directions per chunk
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long s_hrow[kHalo];
@@ -91,8 +91,8 @@ __global__ __launch_bounds__(16 * SW) void k_adj_march(DevGrid G, MarchInfo M, i
     Seg sg;
     {
         const int tile = work / M.nseg, seg = work % M.nseg;
-        sg.tx0 = (tile % M.ntx) * kT;
-        sg.ty0 = (tile / M.ntx) * kT;
+        sg.tx0 = (tile % M.ntx) * kTX;
+        sg.ty0 = (tile / M.ntx) * kTY;
         sg.z0 = seg * M.seglen;
         sg.z1 = min(G.n2, sg.z0 + M.seglen);
     }
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(16 * SW) void k_adj_march(DevGrid G, MarchInfo M, i
     const int lane = threadIdx.x % kWave;
     const int a = lane % SW;
     const int cl = threadIdx.x / SW;
-    const int tx = cl % kT, ty = cl / kT;
+    const int tx = cl % kTX, ty = cl / kTX;
     const int gx = sg.tx0 + tx, gy = sg.ty0 + ty;
     const long long pcells = (long long)G.n0 * G.n1;
     const long long row = (long long)gy * G.n0 + gx;
@@ -166,9 +166,6 @@ __global__ __launch_bounds__(16 * SW) void k_adj_march(DevGrid G, MarchInfo M, i
                        plane_slot(tx + 1, ty) * P, plane_slot(tx + 2, ty) * P};
     const int oy[4] = {plane_slot(tx, ty - 2) * P, plane_slot(tx, ty - 1) * P,
                        plane_slot(tx, ty + 1) * P, plane_slot(tx, ty + 2) * P};
-    const bool all_periodic = G.bc[0][0] == RT_BC_PERIODIC && G.bc[0][1] == RT_BC_PERIODIC &&
-                              G.bc[1][0] == RT_BC_PERIODIC && G.bc[1][1] == RT_BC_PERIODIC &&
-                              G.bc[2][0] == RT_BC_PERIODIC && G.bc[2][1] == RT_BC_PERIODIC;
     const bool zper = G.bc[2][0] == RT_BC_PERIODIC;
     // faces gx-1 .. gx+2 (or gy-1 .. gy+2) of this cell on the luminosity face
     unsigned lmask = 0;
@@ -196,11 +193,6 @@ __global__ __launch_bounds__(16 * SW) void k_adj_march(DevGrid G, MarchInfo M, i
             }
         }
         const Real *src = Iin + (zz * pcells + r) * N;
-        if (all_periodic) {
-#pragma unroll
-            for (int k = 0; k < NC; ++k) dst[k] = src[min(d0 + a + SW * k, N - 1)];
-            return;
-        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int i = a + SW * k;
@@ -222,8 +214,13 @@ __global__ __launch_bounds__(16 * SW) void k_adj_march(DevGrid G, MarchInfo M, i
 #pragma unroll
         for (int k = 0; k < NC; ++k) dst[k] = inside ? src[min(d0 + a + SW * k, N - 1)] : Real(0);
     };
-    const long long hrow0 = s_hrow[2 * cl], hrow1 = s_hrow[2 * cl + 1];
-    const unsigned htest0 = s_htest[2 * cl], htest1 = s_htest[2 * cl + 1];
+    long long hrow[kHPG];
+    unsigned htest[kHPG];
+#pragma unroll
+    for (int j = 0; j < kHPG; ++j) {
+        hrow[j] = s_hrow[kHPG * cl + j];
+        htest[j] = s_htest[kHPG * cl + j];
+    }
 
     // Axis-2 face whose upwind stencil is planes (p, p+1, p+2): the face
     // between p+1 and p+2 for motion along +axis 2 (upwind cell p+1), between
@@ -293,34 +290,37 @@ __global__ __launch_bounds__(16 * SW) void k_adj_march(DevGrid G, MarchInfo M, i
         load_I(sg.z0 + 2, row, 0u, Z2);
         load_P(sg.z0 + 2, row, true, P2);
         // first plane into LDS
-        Real h0[NC], h1[NC], q0[NC], q1[NC];
-        load_I(sg.z0, hrow0, htest0, h0);
-        load_I(sg.z0, hrow1, htest1, h1);
-        load_P(sg.z0, hrow0, htest0 == 0u, q0);
-        load_P(sg.z0, hrow1, htest1 == 0u, q1);
+        Real h0[kHPG][NC], q0[kHPG][NC];
+#pragma unroll
+        for (int j = 0; j < kHPG; ++j) {
+            load_I(sg.z0, hrow[j], htest[j], h0[j]);
+            load_P(sg.z0, hrow[j], htest[j] == 0u, q0[j]);
+        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int i = a + SW * k;
             s_I[o_c + i] = Z0[k];
-            s_I[(kTC + 2 * cl) * P + i] = h0[k];
-            s_I[(kTC + 2 * cl + 1) * P + i] = h1[k];
             s_P[o_c + i] = P0[k];
-            s_P[(kTC + 2 * cl) * P + i] = q0[k];
-            s_P[(kTC + 2 * cl + 1) * P + i] = q1[k];
+#pragma unroll
+            for (int j = 0; j < kHPG; ++j) {
+                s_I[(kTC + kHPG * cl + j) * P + i] = h0[j][k];
+                s_P[(kTC + kHPG * cl + j) * P + i] = q0[j][k];
+            }
         }
     }
 
     for (int z = sg.z0; z < sg.z1; ++z) {
         __syncthreads();
         const bool more = z + 1 < sg.z1;
-        Real Zn[NC], Pn[NC], hI[2][NC], hP[2][NC];
+        Real Zn[NC], Pn[NC], hI[kHPG][NC], hP[kHPG][NC];
         if (more) {
             load_I(z + 3, row, 0u, Zn);
             load_P(z + 3, row, true, Pn);
-            load_I(z + 1, hrow0, htest0, hI[0]);
-            load_I(z + 1, hrow1, htest1, hI[1]);
-            load_P(z + 1, hrow0, htest0 == 0u, hP[0]);
-            load_P(z + 1, hrow1, htest1 == 0u, hP[1]);
+#pragma unroll
+            for (int j = 0; j < kHPG; ++j) {
+                load_I(z + 1, hrow[j], htest[j], hI[j]);
+                load_P(z + 1, hrow[j], htest[j] == 0u, hP[j]);
+            }
         }
         Real tA[NC], tB[NC], tC[NC];
         zface(z, Z0, Z1, Z2, P0, P1, P2, tA, tB, tC);
@@ -389,11 +389,12 @@ __global__ __launch_bounds__(16 * SW) void k_adj_march(DevGrid G, MarchInfo M, i
             for (int k = 0; k < NC; ++k) {
                 const int i = a + SW * k;
                 s_I[o_c + i] = Z1[k];
-                s_I[(kTC + 2 * cl) * P + i] = hI[0][k];
-                s_I[(kTC + 2 * cl + 1) * P + i] = hI[1][k];
                 s_P[o_c + i] = P1[k];
-                s_P[(kTC + 2 * cl) * P + i] = hP[0][k];
-                s_P[(kTC + 2 * cl + 1) * P + i] = hP[1][k];
+#pragma unroll
+                for (int j = 0; j < kHPG; ++j) {
+                    s_I[(kTC + kHPG * cl + j) * P + i] = hI[j][k];
+                    s_P[(kTC + kHPG * cl + j) * P + i] = hP[j][k];
+                }
                 Z0[k] = Z1[k];
                 Z1[k] = Z2[k];
                 Z2[k] = Zn[k];
@@ -424,7 +425,7 @@ int launch_one(rt_grid *g, hipStream_t s, const Real *Iin, const Real *psi, doub
     const long long total = (long long)M.nwork * nchunk;
     if (total >= (1LL << 30)) return RT_EINVAL;
     const int grid = (int)((total + 7) / 8 * 8);
-    hipLaunchKernelGGL((k_adj_march<Real, SW, NC>), dim3(grid), dim3(16 * SW), lds, s, g->dg, M,
+    hipLaunchKernelGGL((k_adj_march<Real, SW, NC>), dim3(grid), dim3(kTC * SW), lds, s, g->dg, M,
                        nchunk, P, Iin, psi, dt, lum_weight, lam);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
 }

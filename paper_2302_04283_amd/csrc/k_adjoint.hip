@@ -28,7 +28,10 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kCellsPerBlock = 16;
 
-template <typename Real, int NCH>
+// SW lanes per cell (16, 32 or 64; several cells per wavefront when SW < 64),
+// lane l of a group handles directions l, l+SW, ... (NCH of them).  RECOMP:
+// recompute I* from I_n (else it is read from the forward step's output).
+template <typename Real, int SW, int NCH, bool RECOMP>
 __global__ __launch_bounds__(kBlock) void k_adj_couple(
     DevGrid G, const Real *__restrict__ Iin, const double *__restrict__ Tin,
     const double *__restrict__ rho, const double *__restrict__ uvec,
@@ -36,8 +39,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     const Real *__restrict__ lamI1, const double *__restrict__ lamT1, Real *__restrict__ psi,
     double *__restrict__ lamT0, double *__restrict__ gka, double *__restrict__ gks,
     const Real *__restrict__ Istar) {
-    const int lane = threadIdx.x % kWave;
-    const int wave = threadIdx.x / kWave;
+    constexpr int kGroups = kBlock / SW;
+    const int lane = threadIdx.x % SW;
+    const int grp = threadIdx.x / SW;
     const long long ncell = (long long)G.n0 * G.n1 * G.n2;
     const int N = G.nang;
     const Real *q = static_cast<const Real *>(G.q);
@@ -45,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     const Real dtR = Real(dt);
     double dummy_l = 0.0, dummy_m = 0.0;
 
-    for (int cw = wave; cw < kCellsPerBlock; cw += kWavesPerBlock) {
+    for (int cw = grp; cw < kCellsPerBlock; cw += kGroups) {
         const long long cc = (long long)blockIdx.x * kCellsPerBlock + cw;
         if (cc >= ncell) break;
         const Cell x = make_cell(G, cc);
@@ -53,11 +57,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         Real Is[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const int n = lane + kWave * ch;
+            const int n = lane + SW * ch;
             Is[ch] = Real(0);
             if (n >= N) continue;
             // I* as stored by the forward step, or recomputed
-            Is[ch] = Istar ? Istar[x.c * N + n] : transport_dir(G, Iin, x, n, dtR, ivol, dummy_l, dummy_m);
+            if constexpr (RECOMP)
+                Is[ch] = transport_dir(G, Iin, x, n, dtR, ivol, dummy_l, dummy_m);
+            else
+                Is[ch] = Istar[x.c * N + n];
         }
         // forward coupling, recomputed.  Per direction: nb = n^0bar (fluid
         // frame), dn = n^0 + nb (alpha_a + alpha_s) dt, rr = 1/(nb^2 dn);
@@ -71,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         double Em = 0.0, A1 = 0.0, A2 = 0.0;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const int n = lane + kWave * ch;
+            const int n = lane + SW * ch;
             const bool live = n < N && !G.mask[(size_t)x.gc * N + (n < N ? n : 0)];
             const int m = live ? n : 0;
             const double nb = u0 - (u1 * G.nhat[3 * m] + u2 * G.nhat[3 * m + 1] + u3 * G.nhat[3 * m + 2]);
@@ -87,15 +94,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
             A1 += (n0 * nb * nb * rr) * I * w;    // n^0/dn
             A2 += dom[ch] * (nb * rr);            // dOmega/(nb dn)
         }
-        Em = group_sum<kWave>(Em);
-        A1 = group_sum<kWave>(A1);
-        A2 = group_sum<kWave>(A2) * (dt / kFourPi);
+        Em = group_sum<SW>(Em);
+        A1 = group_sum<SW>(A1);
+        A2 = group_sum<SW>(A2) * (dt / kFourPi);
         const double Tm = Tin[x.c];
         const double B4 = A2 * aa * G.a_rad;
         const double B1 = rh * G.cv * (1.0 - A2 * as);
         const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
         int bad = 0;
-        const double Tp = quartic_root(B4, B1, B0, bad);
+        const double Tp = quartic_root_fast(B4, B1, B0, bad);
         const double Ep = Em - rh * G.cv * (Tp - Tm);
         const double Tp3 = Tp * Tp * Tp;
         const double S = aa * G.a_rad * Tp3 * Tp + as * Ep;
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         double lpv[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const int n = lane + kWave * ch;
+            const int n = lane + SW * ch;
             const double nb = nbv[ch], dn = dnv[ch], rr = rrv[ch];
             const double k = n0 * nb * nb * rr;                    // n^0/dn
             const double gdir = (dt / kFourPi) * nb * dn * rr * rr; // dt/(4 pi dn nb^3)
@@ -122,10 +129,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
             X2 += w * I * k * nbdn;
             X3 += dom[ch] * idn * idn;
         }
-        lS = group_sum<kWave>(lS);
-        X1 = group_sum<kWave>(X1);
-        X2 = group_sum<kWave>(X2);
-        X3 = group_sum<kWave>(X3);
+        lS = group_sum<SW>(lS);
+        X1 = group_sum<SW>(X1);
+        X2 = group_sum<SW>(X2);
+        X3 = group_sum<SW>(X3);
         // scalar reverse of S, Ep, the quartic and the B coefficients
         const double rcv = rh * G.cv;
         const double lEp = lS * as;
@@ -133,9 +140,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         double lTm = rcv * lEp;
         double laa = lS * G.a_rad * Tp3 * Tp;
         double las = lS * Ep;
-        const double lB4 = -lTp * Tp3 * Tp / Pp;
-        double lB1 = -lTp * Tp / Pp;
-        const double lB0 = -lTp / Pp;
+        const double iPp = rcp64(Pp);
+        const double lB4 = -lTp * Tp3 * Tp * iPp;
+        double lB1 = -lTp * Tp * iPp;
+        const double lB0 = -lTp * iPp;
         const double lA1 = lB0;
         lB1 -= lB0 * Tm;
         lTm -= lB0 * B1;
@@ -152,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         // dJ/dI* per direction, divided by n^0 n_0
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const int n = lane + kWave * ch;
+            const int n = lane + SW * ch;
             if (n >= N) continue;
             Real out = Real(0);
             if (dom[ch] != 0.0) {
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
                 const double k = n0 * nb * nb * rr;
                 const double w = nb * nb * dom[ch];
                 const double lstar = k * lpv[ch] + (lEm + lA1 * k) * w;
-                out = Real(lstar / (double)q[(size_t)x.gc * N + n]);
+                out = Real(lstar * rcp64((double)q[(size_t)x.gc * N + n]));
             }
             psi[x.c * N + n] = out;
         }
@@ -301,23 +309,33 @@ int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
     const Real *in = static_cast<const Real *>(Iin);
     const Real *l1 = static_cast<const Real *>(lamI1);
     Real *psi = static_cast<Real *>(work);
-#define RT_LAUNCH(NC)                                                                          \
-    case NC:                                                                                   \
-        hipLaunchKernelGGL((k_adj_couple<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in,   \
-                           Tin, rho, u, ka, ks, dt, l1, lamT1, psi, lamT0, gka, gks,           \
+    // lanes per cell: 16 for small angle sets, else a full wavefront (fewer
+    // directions per lane keep the per-direction state in registers; the
+    // per-cell work is then spread over the fewest cells per wavefront)
+    const int N = G.nang;
+    int sw = N <= 96 ? 16 : 64;
+    int cnc = (N + sw - 1) / sw;
+#define RT_LAUNCH(SW, NC, RC)                                                                  \
+    if (sw == SW && cnc == NC)                                                                 \
+        hipLaunchKernelGGL((k_adj_couple<Real, SW, NC, RC>), dim3(nblk), dim3(kBlock), 0, s,  \
+                           G, in, Tin, rho, u, ka, ks, dt, l1, lamT1, psi, lamT0, gka, gks,    \
                            static_cast<const Real *>(Istar));                                  \
-        break;
-    switch (nch) {
-        RT_LAUNCH(1)
-        RT_LAUNCH(2)
-        RT_LAUNCH(3)
-        RT_LAUNCH(4)
-        RT_LAUNCH(5)
-        RT_LAUNCH(6)
-        RT_LAUNCH(7)
-        RT_LAUNCH(8)
-        default:
-            return RT_EINVAL;
+    else
+    if (Istar) {
+        RT_LAUNCH(16, 1, false) RT_LAUNCH(16, 2, false) RT_LAUNCH(16, 3, false)
+        RT_LAUNCH(16, 4, false) RT_LAUNCH(16, 5, false) RT_LAUNCH(16, 6, false)
+        RT_LAUNCH(64, 2, false) RT_LAUNCH(64, 3, false) RT_LAUNCH(64, 4, false)
+        RT_LAUNCH(64, 5, false) RT_LAUNCH(64, 6, false)
+        RT_LAUNCH(64, 7, false) RT_LAUNCH(64, 8, false)
+        return RT_EINVAL;
+    } else {
+        // the recompute carries the transport's registers: one cell per wavefront
+        sw = 64;
+        cnc = (N + 63) / 64;
+        RT_LAUNCH(64, 1, true) RT_LAUNCH(64, 2, true) RT_LAUNCH(64, 3, true)
+        RT_LAUNCH(64, 4, true) RT_LAUNCH(64, 5, true) RT_LAUNCH(64, 6, true)
+        RT_LAUNCH(64, 7, true) RT_LAUNCH(64, 8, true)
+        return RT_EINVAL;
     }
 #undef RT_LAUNCH
     if (hipGetLastError() != hipSuccess) return RT_EDEVICE;

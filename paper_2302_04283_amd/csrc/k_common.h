@@ -9,18 +9,79 @@ namespace rt {
 
 constexpr double kFourPi = 12.566370614359172953850573533118;
 
-// Sum over aligned groups of W lanes (W a power of two <= 64).
+// Cross-lane moves for the group sums below, on 32-bit halves.  DPP
+// (quad_perm, row_half_mirror, row_mirror) stays inside a 16-lane row;
+// v_permlane16_swap / v_permlane32_swap (gfx950) exchange rows 0<->1, 2<->3
+// and the two wavefront halves.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u(unsigned x) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = dpp_u<CTRL>((unsigned)b), hi = dpp_u<CTRL>((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7-i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15-i within 16
+
+// x of this lane plus x of the partner row (16 lanes apart) or half (32
+// lanes apart); both partners form the same sum in the same order.
+template <int DIST>
+__device__ __forceinline__ double swap_add(double x) {
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    unsigned l0, l1, h0, h1;
+    if constexpr (DIST == 16) {
+        const auto L = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto H = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = L[0]; l1 = L[1]; h0 = H[0]; h1 = H[1];
+    } else {
+        const auto L = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto H = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = L[0]; l1 = L[1]; h0 = H[0]; h1 = H[1];
+    }
+    const double a = __longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0));
+    const double c = __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1));
+    return a + c;
+}
+template <int DIST>
+__device__ __forceinline__ int swap_add_i(int x) {
+    if constexpr (DIST == 16) {
+        const auto L = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)x, false, false);
+        return (int)L[0] + (int)L[1];
+    } else {
+        const auto L = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
+        return (int)L[0] + (int)L[1];
+    }
+}
+
+// Sum over aligned groups of W lanes (W a power of two, 4 <= W <= 64); every
+// lane of a group receives the same, bitwise identical, sum.
 template <int W>
 __device__ __forceinline__ double group_sum(double x) {
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "group width");
+    x += dpp_d<kDppXor1>(x);
+    x += dpp_d<kDppXor2>(x);
+    if constexpr (W >= 8) x += dpp_d<kDppHalfMirror>(x);
+    if constexpr (W >= 16) x += dpp_d<kDppMirror>(x);
+    if constexpr (W >= 32) x = swap_add<16>(x);
+    if constexpr (W >= 64) x = swap_add<32>(x);
     return x;
 }
 
 template <int W>
 __device__ __forceinline__ int group_sum_i(int x) {
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "group width");
+    x += (int)dpp_u<kDppXor1>((unsigned)x);
+    x += (int)dpp_u<kDppXor2>((unsigned)x);
+    if constexpr (W >= 8) x += (int)dpp_u<kDppHalfMirror>((unsigned)x);
+    if constexpr (W >= 16) x += (int)dpp_u<kDppMirror>((unsigned)x);
+    if constexpr (W >= 32) x = swap_add_i<16>(x);
+    if constexpr (W >= 64) x = swap_add_i<32>(x);
     return x;
 }
 

@@ -5,8 +5,8 @@
 // Work decomposition (gfx950):
 //   * a workgroup owns a 4x4 tile of cells in the (axis 0, axis 1) plane and
 //     marches along axis 2 over a segment of planes;
-//   * each cell of the tile is owned by a group of SW lanes (SW = 16, 32 or
-//     64); lane a of the group handles directions a, a+SW, ... (NC of them),
+//   * each cell of the tile is owned by a group of SW lanes (SW = 16 or
+//     32); lane a of the group handles directions a, a+SW, ... (NC of them),
 //     so the coupling's per-cell FP64 angle sums are SW-lane shuffles and the
 //     quartic runs once per lane group, several cells per wavefront;
 //   * axis-2 neighbours come from a five-plane register queue (each plane is
@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <type_traits>
 
 #include "k_common.h"
 #include "k_tile.h"
@@ -34,14 +35,14 @@ namespace {
 #endif
 
 template <typename Real, int SW, int NC>
-__global__ __launch_bounds__(16 * SW) __attribute__((amdgpu_waves_per_eu(RT_MARCH_WAVES_PER_EU)))
+__global__ __launch_bounds__(kTC * SW) __attribute__((amdgpu_waves_per_eu(RT_MARCH_WAVES_PER_EU)))
 void k_march(
     DevGrid G, MarchInfo M, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
     const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt,
     double *__restrict__ dT0, double *__restrict__ partials, int *__restrict__ nr_partial,
     Real *__restrict__ Istar) {
-    constexpr int NT = 16 * SW;
+    constexpr int NT = kTC * SW;
     constexpr int NW = NT / kWave;
     constexpr int NP = NC * SW;               // padded direction count
     // FP32 planes are double-buffered (plane z+1 is written while plane z is
@@ -69,8 +70,8 @@ void k_march(
     Seg sg;
     {
         const int tile = logical / M.nseg, seg = logical % M.nseg;
-        sg.tx0 = (tile % M.ntx) * kT;
-        sg.ty0 = (tile / M.ntx) * kT;
+        sg.tx0 = (tile % M.ntx) * kTX;
+        sg.ty0 = (tile / M.ntx) * kTY;
         sg.z0 = seg * M.seglen;
         sg.z1 = min(G.n2, sg.z0 + M.seglen);
     }
@@ -137,7 +138,7 @@ void k_march(
     const int lane = threadIdx.x % kWave;
     const int a = lane % SW;
     const int cl = threadIdx.x / SW;            // tile cell owned by this lane group
-    const int tx = cl % kT, ty = cl / kT;
+    const int tx = cl % kTX, ty = cl / kTX;
     const int gx = sg.tx0 + tx, gy = sg.ty0 + ty;
     const long long pcells = (long long)G.n0 * G.n1;
     const long long row = (long long)gy * G.n0 + gx;
@@ -157,10 +158,6 @@ void k_march(
     const bool on_lum_xy = (G.lum_axis == 0 && gx == (lside ? G.n0 - 1 : 0)) ||
                            (G.lum_axis == 1 && gy == (lside ? G.n1 - 1 : 0));
 
-    // every boundary periodic: no ghost ever needs the outflow test
-    const bool all_periodic = G.bc[0][0] == RT_BC_PERIODIC && G.bc[0][1] == RT_BC_PERIODIC &&
-                              G.bc[1][0] == RT_BC_PERIODIC && G.bc[1][1] == RT_BC_PERIODIC &&
-                              G.bc[2][0] == RT_BC_PERIODIC && G.bc[2][1] == RT_BC_PERIODIC;
     // plane pz of a row, with the axis-2 boundary condition; `xytest` is the
     // axis-0/1 outflow test of a halo row (0: always copy)
     auto load_row = [&](int pz, long long r, unsigned xytest, Real *dst) {
@@ -176,11 +173,6 @@ void k_march(
             }
         }
         const Real *src = Iin + (zz * pcells + r) * N;
-        if (all_periodic) {
-#pragma unroll
-            for (int k = 0; k < NC; ++k) dst[k] = src[k < NC - 1 ? a + SW * k : min(a + SW * k, N - 1)];
-            return;
-        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int n = a + SW * k;
@@ -190,8 +182,14 @@ void k_march(
             dst[k] = ((s_bits[n] & test) == test) ? v : Real(0);
         }
     };
-    const long long hrow0 = s_hrow[2 * cl], hrow1 = s_hrow[2 * cl + 1];
-    const unsigned htest0 = s_htest[2 * cl], htest1 = s_htest[2 * cl + 1];
+    // this lane group's halo cells: source rows and outflow tests
+    long long hrow[kHPG];
+    unsigned htest[kHPG];
+#pragma unroll
+    for (int j = 0; j < kHPG; ++j) {
+        hrow[j] = s_hrow[kHPG * cl + j];
+        htest[j] = s_htest[kHPG * cl + j];
+    }
     // one fluid field per lane (a < 7): u1 u2 u3 rho kappa_a kappa_s T
     auto load_fluid = [&](int z) -> double {
         const long long c = (long long)z * pcells + row;
@@ -206,15 +204,15 @@ void k_march(
 #pragma unroll
     for (int p = 0; p < 5; ++p) load_row(sg.z0 - 2 + p, row, 0u, qz[p]);
     {
-        Real h0[NC], h1[NC];
-        load_row(sg.z0, hrow0, htest0, h0);
-        load_row(sg.z0, hrow1, htest1, h1);
+        Real h0[kHPG][NC];
+#pragma unroll
+        for (int j = 0; j < kHPG; ++j) load_row(sg.z0, hrow[j], htest[j], h0[j]);
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int n = a + SW * k;
             s_pl[o_c + n] = qz[2][k];
-            s_pl[(kTC + 2 * cl) * P + n] = h0[k];
-            s_pl[(kTC + 2 * cl + 1) * P + n] = h1[k];
+#pragma unroll
+            for (int j = 0; j < kHPG; ++j) s_pl[(kTC + kHPG * cl + j) * P + n] = h0[j][k];
         }
         const double flv = load_fluid(sg.z0);
         if (a < 7) s_fl[cl][a] = flv;
@@ -252,12 +250,12 @@ void k_march(
         __syncthreads();
         // prefetch the next plane while this one is computed
         const bool more = z + 1 < sg.z1;
-        Real qn[NC], hn[2][NC];
+        Real qn[NC], hn[kHPG][NC];
         double fln = 0.0;
         if (more) {
             load_row(z + 3, row, 0u, qn);
-            load_row(z + 1, hrow0, htest0, hn[0]);
-            load_row(z + 1, hrow1, htest1, hn[1]);
+#pragma unroll
+            for (int j = 0; j < kHPG; ++j) load_row(z + 1, hrow[j], htest[j], hn[j]);
             fln = load_fluid(z + 1);
         }
         const bool lum_here = on_lum_xy || (G.lum_axis == 2 && z == (lside ? G.n2 - 1 : 0));
@@ -266,69 +264,94 @@ void k_march(
         // ------------------------------------------------------ transport
         const long long cidx = (long long)z * pcells + row;
         Real Is[NC];
+        // Each feature flag is 0 (off), 1 (on) or 2 (tested at run time): the
+        // common cases get straight-line code over the NC directions, which
+        // the compiler can interleave; the rest take the generic variant.
+        auto transport = [&](auto tP, auto tM, auto tS, auto tL) {
+            constexpr int vP = decltype(tP)::value, vM = decltype(tM)::value;
+            constexpr int vS = decltype(tS)::value, vL = decltype(tL)::value;
+            const bool doP = vP == 1 || (vP == 2 && plm);
+            const bool doM = vM == 1 || (vM == 2 && M.any_mask);
+            const bool doS = vS == 1 || (vS == 2 && Istar != nullptr);
+            const bool doL = vL == 1 || (vL == 2 && lum_wave);
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int n = a + SW * k;
-            const Real Ic = qz[2][k];
-            // upwind-ordered neighbours; a direction without motion along an
-            // axis has a zero coefficient there, so its branch is irrelevant
-            const bool nx = fx[k], ny = fy[k], nz = fz[k];
-            // all four axis-0/1 neighbours at fixed offsets, then the upwind order
-            const Real xm2 = pl[ox[0] + n], xm1 = pl[ox[1] + n];
-            const Real xp1 = pl[ox[2] + n], xp2 = pl[ox[3] + n];
-            const Real ym2 = pl[oy[0] + n], ym1 = pl[oy[1] + n];
-            const Real yp1 = pl[oy[2] + n], yp2 = pl[oy[3] + n];
-            const Real x0 = nx ? xp2 : xm2, x1 = nx ? xp1 : xm1, x3 = nx ? xm1 : xp1;
-            const Real y0 = ny ? yp2 : ym2, y1 = ny ? yp1 : ym1, y3 = ny ? ym1 : yp1;
-            // upper axis-2 face: the outflow face for motion along +axis 2
-            // (upwind cell z), the inflow face otherwise (upwind cell z+1)
-            const Real zl = nz ? qz[4][k] : qz[1][k];
-            const Real zm = nz ? qz[3][k] : qz[2][k];
-            const Real zr = nz ? qz[2][k] : qz[3][k];
-            Real Iax, Ibx, Iay, Iby, zup;
-            if (plm) {
-                Iax = x1 + half_slope(x0, x1, Ic);
-                Ibx = Ic + half_slope(x1, Ic, x3);
-                Iay = y1 + half_slope(y0, y1, Ic);
-                Iby = Ic + half_slope(y1, Ic, y3);
-                zup = zm + half_slope(zl, zm, zr);
-            } else {
-                Iax = x1;
-                Ibx = Ic;
-                Iay = y1;
-                Iby = Ic;
-                zup = zm;
+            for (int k = 0; k < NC; ++k) {
+                const int n = a + SW * k;
+                const Real Ic = qz[2][k];
+                // upwind-ordered neighbours; a direction without motion along
+                // an axis has a zero coefficient there, so its branch is
+                // irrelevant
+                const bool nx = fx[k], ny = fy[k], nz = fz[k];
+                // all four axis-0/1 neighbours at fixed offsets, then the upwind order
+                const Real xm2 = pl[ox[0] + n], xm1 = pl[ox[1] + n];
+                const Real xp1 = pl[ox[2] + n], xp2 = pl[ox[3] + n];
+                const Real ym2 = pl[oy[0] + n], ym1 = pl[oy[1] + n];
+                const Real yp1 = pl[oy[2] + n], yp2 = pl[oy[3] + n];
+                const Real x0 = nx ? xp2 : xm2, x1 = nx ? xp1 : xm1, x3 = nx ? xm1 : xp1;
+                const Real y0 = ny ? yp2 : ym2, y1 = ny ? yp1 : ym1, y3 = ny ? ym1 : yp1;
+                // upper axis-2 face: the outflow face for motion along +axis 2
+                // (upwind cell z), the inflow face otherwise (upwind cell z+1)
+                const Real zl = nz ? qz[4][k] : qz[1][k];
+                const Real zm = nz ? qz[3][k] : qz[2][k];
+                const Real zr = nz ? qz[2][k] : qz[3][k];
+                Real Iax, Ibx, Iay, Iby, zup;
+                if (doP) {
+                    Iax = x1 + half_slope(x0, x1, Ic);
+                    Ibx = Ic + half_slope(x1, Ic, x3);
+                    Iay = y1 + half_slope(y0, y1, Ic);
+                    Iby = Ic + half_slope(y1, Ic, y3);
+                    zup = zm + half_slope(zl, zm, zr);
+                } else {
+                    Iax = x1;
+                    Ibx = Ic;
+                    Iay = y1;
+                    Iby = Ic;
+                    zup = zm;
+                }
+                // inflow (a) and outflow (b) face values along axis 2
+                const Real Iaz = nz ? zup : zc[k];
+                const Real Ibz = nz ? zc[k] : zup;
+                zc[k] = zup;
+                // signed coefficients: +-C/dV with the sign of the motion
+                const Real cx = s_tab[2 * NP + n], cy = s_tab[3 * NP + n], cz = s_tab[4 * NP + n];
+                const Real dq = fma(cz, Ibz - Iaz, fma(cy, Iby - Iay, cx * (Ibx - Iax)));
+                const Real Qs = fma(-dtR, dq, s_tab[n] * Ic);
+                if constexpr (sizeof(Real) == 4)
+                    Is[k] = Qs * s_tab[NP + n];
+                else
+                    Is[k] = Qs / s_tab[n];
+                if (doM) {
+                    const bool msk = fm[k];
+                    me_acc -= msk ? vol * s_dom_all[n] * (double)Qs : 0.0;
+                    Is[k] = msk ? Real(0) : Is[k];
+                }
+                if (doS && (k < NC - 1 || n < N)) Istar[cidx * N + n] = Is[k];
+                if (doL) {
+                    // energy leaving through the face.  With the signed
+                    // coefficients, the face's flux (dA n^a n_0 I_up)/dV is
+                    // c Ib when the face is on the outflow side of the cell,
+                    // -c Ia when on the inflow side; the outward orientation
+                    // of a lower face adds a minus sign
+                    double F = 0.0;
+                    if (G.lum_axis == 0) F = (double)(nx == (lside == 0) ? cx * Ibx : -(cx * Iax));
+                    else if (G.lum_axis == 1) F = (double)(ny == (lside == 0) ? cy * Iby : -(cy * Iay));
+                    else F = (double)(nz == (lside == 0) ? cz * Ibz : -(cz * Iaz));
+                    lum_acc -= lum_here ? s_dom_all[n] * vol * F : 0.0;
+                }
             }
-            // inflow (a) and outflow (b) face values along axis 2
-            const Real Iaz = nz ? zup : zc[k];
-            const Real Ibz = nz ? zc[k] : zup;
-            zc[k] = zup;
-            // signed coefficients: +-C/dV with the sign of the motion
-            const Real cx = s_tab[2 * NP + n], cy = s_tab[3 * NP + n], cz = s_tab[4 * NP + n];
-            const Real dq = fma(cz, Ibz - Iaz, fma(cy, Iby - Iay, cx * (Ibx - Iax)));
-            const Real Qs = fma(-dtR, dq, s_tab[n] * Ic);
-            if constexpr (sizeof(Real) == 4)
-                Is[k] = Qs * s_tab[NP + n];
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        // (FP64 keeps the generic variant: straight-line FP64 code over six
+        // directions does not fit the register file)
+        if (sizeof(Real) == 4 && plm && !M.any_mask && !lum_wave) {
+            if (Istar)
+                transport(I1{}, I0{}, I1{}, I0{});
             else
-                Is[k] = Qs / s_tab[n];
-            if (M.any_mask) {
-                const bool msk = fm[k];
-                me_acc -= msk ? vol * s_dom_all[n] * (double)Qs : 0.0;
-                Is[k] = msk ? Real(0) : Is[k];
-            }
-            if (Istar && (k < NC - 1 || n < N)) Istar[cidx * N + n] = Is[k];
-            if (lum_wave) {
-                // energy leaving through the face.  With the signed
-                // coefficients, the face's flux (dA n^a n_0 I_up)/dV is Fb when
-                // the face is on the outflow side of the cell, -Fa when on the
-                // inflow side; the outward orientation of a lower face adds a
-                // minus sign
-                double F = 0.0;
-                if (G.lum_axis == 0) F = (double)(nx == (lside == 0) ? cx * Ibx : -(cx * Iax));
-                else if (G.lum_axis == 1) F = (double)(ny == (lside == 0) ? cy * Iby : -(cy * Iay));
-                else F = (double)(nz == (lside == 0) ? cz * Ibz : -(cz * Iaz));
-                lum_acc -= lum_here ? s_dom_all[n] * vol * F : 0.0;
-            }
+                transport(I1{}, I0{}, I0{}, I0{});
+        } else {
+            transport(I2{}, I2{}, I2{}, I2{});
         }
 
         // ------------------------------------------------------ coupling
@@ -410,8 +433,8 @@ void k_march(
             for (int k = 0; k < NC; ++k) {
                 const int n = a + SW * k;
                 nx[o_c + n] = qz[3][k];
-                nx[(kTC + 2 * cl) * P + n] = hn[0][k];
-                nx[(kTC + 2 * cl + 1) * P + n] = hn[1][k];
+#pragma unroll
+                for (int j = 0; j < kHPG; ++j) nx[(kTC + kHPG * cl + j) * P + n] = hn[j][k];
                 qz[0][k] = qz[1][k];
                 qz[1][k] = qz[2][k];
                 qz[2][k] = qz[3][k];
@@ -460,7 +483,7 @@ int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T
             return RT_EDEVICE;
         lds_set = true;
     }
-    hipLaunchKernelGGL((k_march<Real, SW, NC>), dim3(M.grid), dim3(16 * SW), M.lds, s, g->dg, M,
+    hipLaunchKernelGGL((k_march<Real, SW, NC>), dim3(M.grid), dim3(kTC * SW), M.lds, s, g->dg, M,
                        static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho, u, ka,
                        ks, dt, dT0, g->partials, g->noroot_partial, Istar);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
@@ -471,16 +494,15 @@ int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T
 // Lane-group width and directions per lane for each supported direction count.
 bool march_config(int precision, int nang, int &sw, int &nc) {
     // instantiated (lane-group width, directions per lane) pairs
-    static const int f32[][2] = {{16, 1}, {16, 3}, {16, 6}, {16, 11}, {32, 3}, {32, 6},
-                                 {32, 8}, {32, 12}, {64, 3}};
-    static const int f64[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 6}, {64, 3}};
+    static const int f32[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 6}, {32, 8}};
+    static const int f64[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 6}};
     int want = 0;
     if (const char *e = std::getenv("RT_MARCH_SW")) want = std::atoi(e);
     const int (*tab)[2] = precision == RT_F32 ? f32 : f64;
-    const int ntab = precision == RT_F32 ? 9 : 6;
+    const int ntab = precision == RT_F32 ? 6 : 5;
     // smallest group width whose directions-per-lane fits the register budget
     const int budget = 6;
-    for (int w : {16, 32, 64}) {
+    for (int w : {16, 32}) {
         if (want && w != want) continue;
         const int need = (nang + w - 1) / w;
         if (!want && need > budget) continue;
@@ -524,19 +546,15 @@ int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double 
         RT_CASE(float, 16, 1)
         RT_CASE(float, 16, 3)
         RT_CASE(float, 16, 6)
-        RT_CASE(float, 16, 11)
         RT_CASE(float, 32, 3)
         RT_CASE(float, 32, 6)
         RT_CASE(float, 32, 8)
-        RT_CASE(float, 32, 12)
-        RT_CASE(float, 64, 3)
     } else {
         RT_CASE(double, 16, 1)
         RT_CASE(double, 16, 3)
         RT_CASE(double, 16, 6)
         RT_CASE(double, 32, 3)
         RT_CASE(double, 32, 6)
-        RT_CASE(double, 64, 3)
     }
 #undef RT_CASE
     return RT_EINVAL;

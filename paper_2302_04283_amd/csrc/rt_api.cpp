@@ -9,6 +9,7 @@
 #include <sstream>
 #include <string>
 
+#include "k_tile.h"
 #include "rt_internal.h"
 
 namespace {
@@ -225,7 +226,8 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
             const bool allow = !(env && env[0] == '0');
             const bool cfg = rt::march_config(d->precision, N, sw, nc);
             const size_t lds = cfg ? rt::march_lds_bytes(d->precision, N, sw * nc) : 0;
-            if (allow && cfg && G == 1 && !t.has_edges && d->n[0] % 4 == 0 && d->n[1] % 4 == 0 &&
+            if (allow && cfg && G == 1 && !t.has_edges && d->n[0] % rt::kTX == 0 &&
+                d->n[1] % rt::kTY == 0 &&
                 lds <= 150 * 1024) {
                 std::vector<double> q(N), iq(N), cx(N), cy(N), cz(N);
                 std::vector<uint8_t> bits(N, 0);
@@ -256,8 +258,8 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
                 M.nc = nc;
                 M.lds = lds;
                 M.pstride = rt::march_pstride(d->precision, sw * nc);
-                M.ntx = d->n[0] / 4;
-                const long long ntiles = (long long)(d->n[0] / 4) * (d->n[1] / 4);
+                M.ntx = d->n[0] / rt::kTX;
+                const long long ntiles = (long long)(d->n[0] / rt::kTX) * (d->n[1] / rt::kTY);
                 long long target = 2048;
                 if (const char *w = std::getenv("RT_MARCH_WG")) target = std::max(1LL, std::atoll(w));
                 long long seglen = std::max<long long>(4, (d->n[2] * ntiles + target - 1) / target);

@@ -187,32 +187,83 @@ PER = [(0, 0)] * 3
 OUT = [(1, 1)] * 3
 
 
-@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
-@pytest.mark.parametrize("bc,lum_axis,lum_side", [
+BOUNDARY_CASES = [
     (PER, 0, 1), (PER, 1, 0), (PER, 2, 1), (PER, 2, 0),
     (OUT, 0, 0), (OUT, 1, 1), (OUT, 2, 0), (OUT, 2, 1),
-    ([(0, 0), (1, 1), (0, 0)], 1, 0)])
-def test_tiled_adjoint_boundaries_and_luminosity_faces(bc, lum_axis, lum_side, prec):
-    """The tiled transport adjoint (uniform geometry) against the oracle's
-    reference gradient for every luminosity face and both boundary kinds."""
+    ([(0, 0), (1, 1), (0, 0)], 1, 0)]
+
+
+def _bc_tag(bc):
+    return "per" if bc == PER else ("out" if bc == OUT else "mixed")
+
+
+@pytest.mark.parametrize("bc,lum_axis,lum_side", BOUNDARY_CASES)
+def test_tiled_adjoint_boundaries_and_luminosity_faces(bc, lum_axis, lum_side):
+    """The tiled transport adjoint (uniform geometry, FP64) against the
+    oracle's reference gradient for every luminosity face and both boundary
+    kinds."""
     p = _tiled_problem(bc, lum_axis, lum_side)
     S = O.setup(p)
     dt = O.max_dt(S, 0.3)
     steps = 4
     I0 = np.abs(p.initial_intensity()) + 0.1
     ref = GR.reference_gradient(p, I0, p.T, dt, steps)
-    g = rt.Grid(p, prec)
+    g = rt.Grid(p, rt.RT_F64)
     assert g.fast_path
     g.close()
-    got = _gpu_grads(p, prec, steps, dt, 2, I0=I0)
-    tol = 1e-10 if prec == rt.RT_F64 else 1e-4
+    got = _gpu_grads(p, rt.RT_F64, steps, dt, 2, I0=I0)
     errs = {k: _max_rel(got[k], ref[k]) for k in ("kappa_a", "kappa_s", "T0", "I0")}
-    print("[adjoint] tiled bc=%s lum=(%d,%d) %s %s" % (
-        "per" if bc == PER else ("out" if bc == OUT else "mixed"), lum_axis, lum_side,
-        "fp64" if prec == 0 else "fp32", " ".join("e_%s=%.2e" % kv for kv in errs.items())),
+    print("[adjoint] tiled bc=%s lum=(%d,%d) fp64 %s" % (
+        _bc_tag(bc), lum_axis, lum_side, " ".join("e_%s=%.2e" % kv for kv in errs.items())),
         flush=True)
     for k, e in errs.items():
-        assert e <= tol, (k, e)
+        assert e <= 1e-10, (k, e)
+
+
+def _manual_adjoint(g, states, rho, u, ka, ks, dt):
+    I = states[0][0]
+    lamI, lamT = torch.zeros_like(I), torch.zeros_like(states[0][1])
+    work = torch.empty_like(I)
+    gka, gks = torch.zeros_like(lamT), torch.zeros_like(lamT)
+    for Is, Ts in reversed(states):
+        g.step_adjoint(Is, Ts, rho, u, ka, ks, dt, lamI, lamT, lamI, lamT, work, gka, gks)
+    return {"I0": lamI.double().cpu().numpy(), "T0": lamT.cpu().numpy(),
+            "kappa_a": gka.cpu().numpy(), "kappa_s": gks.cpu().numpy()}
+
+
+@pytest.mark.parametrize("bc,lum_axis,lum_side", BOUNDARY_CASES)
+def test_tiled_adjoint_fp32_arithmetic(bc, lum_axis, lum_side):
+    """FP32 adjoint = exact derivative of the FP32 step.  Against the FP64
+    reference it can differ by far more than rounding wherever the FP32
+    trajectory takes the other branch of a van Leer limiter (the gradient of
+    a limited scheme jumps there; on the periodic, luminosity-face-0 case of
+    this set one direction flips and the FP32 gradient is 1e-2 off in
+    max-norm).  So the FP32 adjoint arithmetic is checked against the FP64
+    library adjoint evaluated on the same FP32 trajectory (1e-5), and the
+    FP32 trajectory against the oracle (forward parity)."""
+    p = _tiled_problem(bc, lum_axis, lum_side)
+    dt = O.max_dt(O.setup(p), 0.3)
+    I0 = np.abs(p.initial_intensity()) + 0.1
+    g32, g64 = rt.Grid(p, rt.RT_F32), rt.Grid(p, rt.RT_F64)
+    assert g32.fast_path and g64.fast_path
+    rho, u, ka, ks = _t(p.rho), _t(p.u_tet), _t(p.kappa_a), _t(p.kappa_s)
+    I, T = _t(I0).float(), _t(p.T)
+    states = []
+    for _ in range(4):
+        Ib = torch.empty_like(I)
+        states.append((I.clone(), T.clone()))
+        g32.step(I, Ib, T, rho, u, ka, ks, dt)
+        I = Ib
+    a = _manual_adjoint(g32, states, rho, u, ka, ks, dt)
+    b = _manual_adjoint(g64, [(Is.double(), Ts) for Is, Ts in states], rho, u, ka, ks, dt)
+    g32.close()
+    g64.close()
+    errs = {k: _max_rel(a[k], b[k]) for k in ("kappa_a", "kappa_s", "T0", "I0")}
+    print("[adjoint] tiled fp32 arithmetic bc=%s lum=(%d,%d) %s" % (
+        _bc_tag(bc), lum_axis, lum_side, " ".join("e_%s=%.2e" % kv for kv in errs.items())),
+        flush=True)
+    for k, e in errs.items():
+        assert e <= 1e-5, (k, e)
 
 
 @pytest.mark.parametrize("nlev,shape,seglen", [(4, (8, 4, 7), "3"), (2, (4, 8, 5), "2"),
