@@ -48,12 +48,28 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     const Real *invV = static_cast<const Real *>(G.invV);
     const Real dtR = Real(dt);
     double dummy_l = 0.0, dummy_m = 0.0;
-
+    const bool uniform_geo = G.g0 == 1 && G.g1 == 1 && G.g2 == 1;
     for (int cw = grp; cw < kCellsPerBlock; cw += kGroups) {
         const long long cc = (long long)blockIdx.x * kCellsPerBlock + cw;
         if (cc >= ncell) break;
-        const Cell x = make_cell(G, cc);
-        const Real ivol = invV[x.gc];
+        Cell x;
+        if constexpr (RECOMP) {
+            x = make_cell(G, cc);
+        } else {
+            // only the cell and its geometry index are needed (cell counts
+            // stay far below 2^32, so 32-bit index arithmetic suffices)
+            x.c = cc;
+            x.gc = 0;
+            if (!uniform_geo) {
+                const unsigned cu = (unsigned)cc, n0 = (unsigned)G.n0, n1 = (unsigned)G.n1;
+                const unsigned t = cu / n0;
+                x.i = (int)(cu - t * n0);
+                x.j = (int)(t % n1);
+                x.k = (int)(t / n1);
+                x.gc = ((G.g2 > 1 ? x.k : 0) * G.g1 + (G.g1 > 1 ? x.j : 0)) * G.g0 +
+                       (G.g0 > 1 ? x.i : 0);
+            }
+        }
         Real Is[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
@@ -62,41 +78,46 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
             if (n >= N) continue;
             // I* as stored by the forward step, or recomputed
             if constexpr (RECOMP)
-                Is[ch] = transport_dir(G, Iin, x, n, dtR, ivol, dummy_l, dummy_m);
+                Is[ch] = transport_dir(G, Iin, x, n, dtR, invV[x.gc], dummy_l, dummy_m);
             else
                 Is[ch] = Istar[x.c * N + n];
         }
         // forward coupling, recomputed.  Per direction: nb = n^0bar (fluid
-        // frame), dn = n^0 + nb (alpha_a + alpha_s) dt, rr = 1/(nb^2 dn);
-        // every quotient below is a product with rr
+        // frame), dn = n^0 + nb (alpha_a + alpha_s) dt, rr = 1/(nb^2 dn) and
+        // from it idn = 1/dn, k = n^0/dn, r1 = 1/(nb dn); w = nb^2 dOmega
         const double u1 = uvec[3 * x.c], u2 = uvec[3 * x.c + 1], u3 = uvec[3 * x.c + 2];
-        const double u0 = sqrt(1.0 + u1 * u1 + u2 * u2 + u3 * u3);
+        const double u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
         const double rh = rho[x.c];
-        const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh, aE = aa + as;
+        const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh;
+        const double tau = (aa + as) * dt;
         const double n0 = G.n0u[x.gc];
-        double nbv[NCH], dnv[NCH], rrv[NCH], dom[NCH];
-        double Em = 0.0, A1 = 0.0, A2 = 0.0;
+        double nbv[NCH], dnv[NCH], rrv[NCH], idnv[NCH], kv[NCH], wv[NCH], Iv[NCH], dom[NCH];
+        double sf[3] = {0.0, 0.0, 0.0};   // Em, A1, A2
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + SW * ch;
             const bool live = n < N && !G.mask[(size_t)x.gc * N + (n < N ? n : 0)];
             const int m = live ? n : 0;
-            const double nb = u0 - (u1 * G.nhat[3 * m] + u2 * G.nhat[3 * m + 1] + u3 * G.nhat[3 * m + 2]);
-            const double dn = n0 + nb * aE * dt;
-            const double rr = rcp64(nb * nb * dn);
+            const double nb = u0 - fma(u1, G.nhat[3 * m], fma(u2, G.nhat[3 * m + 1], u3 * G.nhat[3 * m + 2]));
+            const double nb2 = nb * nb;
+            const double dn = fma(nb, tau, n0);
+            const double rr = rcp64(nb2 * dn);
+            const double idn = nb2 * rr;
+            dom[ch] = live ? G.domega[m] : 0.0;   // zero weight: masked or padding
             nbv[ch] = nb;
             dnv[ch] = dn;
             rrv[ch] = rr;
-            dom[ch] = live ? G.domega[m] : 0.0;   // zero weight: masked or padding
-            const double w = nb * nb * dom[ch];
-            const double I = (double)Is[ch];
-            Em += I * w;
-            A1 += (n0 * nb * nb * rr) * I * w;    // n^0/dn
-            A2 += dom[ch] * (nb * rr);            // dOmega/(nb dn)
+            idnv[ch] = idn;
+            kv[ch] = n0 * idn;
+            wv[ch] = nb2 * dom[ch];
+            Iv[ch] = (double)Is[ch];
+            const double Iw = Iv[ch] * wv[ch];
+            sf[0] += Iw;
+            sf[1] = fma(kv[ch], Iw, sf[1]);
+            sf[2] = fma(dom[ch], nb * rr, sf[2]);
         }
-        Em = group_sum<SW>(Em);
-        A1 = group_sum<SW>(A1);
-        A2 = group_sum<SW>(A2) * (dt / kFourPi);
+        group_sum_v<SW, 3>(sf);
+        const double Em = sf[0], A1 = sf[1], A2 = sf[2] * (dt / kFourPi);
         const double Tm = Tin[x.c];
         const double B4 = A2 * aa * G.a_rad;
         const double B1 = rh * G.cv * (1.0 - A2 * as);
@@ -107,32 +128,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         const double Tp3 = Tp * Tp * Tp;
         const double S = aa * G.a_rad * Tp3 * Tp + as * Ep;
         const double Pp = 4.0 * B4 * Tp3 + B1;
-        // adjoint sums over directions
+        // adjoint sums over directions: lS, X1, X2, X3
         const bool beam_cell = G.beam != nullptr && G.beam[x.c];
-        double lS = 0.0, X1 = 0.0, X2 = 0.0, X3 = 0.0;
+        const double c4 = dt / kFourPi;
+        double sr[4] = {0.0, 0.0, 0.0, 0.0};
         double lpv[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + SW * ch;
-            const double nb = nbv[ch], dn = dnv[ch], rr = rrv[ch];
-            const double k = n0 * nb * nb * rr;                    // n^0/dn
-            const double gdir = (dt / kFourPi) * nb * dn * rr * rr; // dt/(4 pi dn nb^3)
-            const double nbdn = nb * nb * nb * rr;                  // nb/dn
-            const double w = nb * nb * dom[ch];
-            const double I = (double)Is[ch];
+            const double nb = nbv[ch], rr = rrv[ch], idn = idnv[ch], k = kv[ch];
+            const double gdir = c4 * (nb * rr) * rr * dnv[ch];   // dt/(4 pi dn nb^3)
+            const double nbdn = nb * idn;                         // nb/dn
             const bool use = n < N && dom[ch] != 0.0 && !(beam_cell && n == G.beam_angle);
             const double lp = use ? (double)lamI1[x.c * N + n] : 0.0;
             lpv[ch] = lp;
-            const double idn = nb * nb * rr;                        // 1/dn
-            lS += lp * gdir;
-            X1 += lp * (I * k + S * gdir) * nbdn;
-            X2 += w * I * k * nbdn;
-            X3 += dom[ch] * idn * idn;
+            sr[0] = fma(lp, gdir, sr[0]);
+            sr[1] = fma(lp * fma(Iv[ch], k, S * gdir), nbdn, sr[1]);
+            sr[2] = fma(wv[ch] * Iv[ch] * k, nbdn, sr[2]);
+            sr[3] = fma(dom[ch] * idn, idn, sr[3]);
         }
-        lS = group_sum<SW>(lS);
-        X1 = group_sum<SW>(X1);
-        X2 = group_sum<SW>(X2);
-        X3 = group_sum<SW>(X3);
+        group_sum_v<SW, 4>(sr);
+        const double lS = sr[0], X1 = sr[1], X2 = sr[2], X3 = sr[3];
         // scalar reverse of S, Ep, the quartic and the B coefficients
         const double rcv = rh * G.cv;
         const double lEp = lS * as;
@@ -164,10 +180,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
             if (n >= N) continue;
             Real out = Real(0);
             if (dom[ch] != 0.0) {
-                const double nb = nbv[ch], rr = rrv[ch];
-                const double k = n0 * nb * nb * rr;
-                const double w = nb * nb * dom[ch];
-                const double lstar = k * lpv[ch] + (lEm + lA1 * k) * w;
+                const double k = kv[ch];
+                const double lstar = fma(k, lpv[ch], fma(lA1, k, lEm) * wv[ch]);
                 out = Real(lstar * rcp64((double)q[(size_t)x.gc * N + n]));
             }
             psi[x.c * N + n] = out;

@@ -73,6 +73,34 @@ __device__ __forceinline__ double group_sum(double x) {
     return x;
 }
 
+// K independent sums over the same groups, step by step interleaved (each
+// cross-lane move then reads a register written several instructions
+// earlier, so no DPP hazard padding is needed).
+template <int W, int K>
+__device__ __forceinline__ void group_sum_v(double (&x)[K]) {
+    static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "group width");
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] += dpp_d<kDppXor1>(x[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] += dpp_d<kDppXor2>(x[k]);
+    if constexpr (W >= 8) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] += dpp_d<kDppHalfMirror>(x[k]);
+    }
+    if constexpr (W >= 16) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] += dpp_d<kDppMirror>(x[k]);
+    }
+    if constexpr (W >= 32) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = swap_add<16>(x[k]);
+    }
+    if constexpr (W >= 64) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = swap_add<32>(x[k]);
+    }
+}
+
 template <int W>
 __device__ __forceinline__ int group_sum_i(int x) {
     static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "group width");

@@ -379,9 +379,13 @@ void k_march(
             kk[k] = Real(kn);
             gg[k] = Real(nb * dn * r * r);             // 1/(dn nb^3)
         }
-        Em = group_sum<SW>(Em);
-        A1 = group_sum<SW>(A1);
-        A2 = group_sum<SW>(A2) * (dt / kFourPi);
+        {
+            double sf[3] = {Em, A1, A2};
+            group_sum_v<SW, 3>(sf);
+            Em = sf[0];
+            A1 = sf[1];
+            A2 = sf[2] * (dt / kFourPi);
+        }
         const double B4 = A2 * aa * G.a_rad;
         const double B1 = rh * G.cv * (1.0 - A2 * as);
         const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
@@ -407,10 +411,14 @@ void k_march(
             out = (beam_cell && n == G.beam_angle) ? Real(G.beam_I) : out;
             if (k < NC - 1 || n < N) dst[n] = out;
         }
-        Mv0 = group_sum<SW>(Mv0);
-        Mv1 = group_sum<SW>(Mv1);
-        Mv2 = group_sum<SW>(Mv2);
-        Mv3 = group_sum<SW>(Mv3);
+        {
+            double sm[4] = {Mv0, Mv1, Mv2, Mv3};
+            group_sum_v<SW, 4>(sm);
+            Mv0 = sm[0];
+            Mv1 = sm[1];
+            Mv2 = sm[2];
+            Mv3 = sm[3];
+        }
         if (a == 0) {
             T[cidx] = Tp;
             nr_acc += bad;

@@ -80,9 +80,13 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
             A1 += (n0 / dn) * I * w2;
             A2 += G.domega[n] / (nb * dn);
         }
-        Em = wave_sum(Em);
-        A1 = wave_sum(A1);
-        A2 = wave_sum(A2) * (dt / kFourPi);
+        {
+            double sf[3] = {Em, A1, A2};
+            group_sum_v<kWave, 3>(sf);
+            Em = sf[0];
+            A1 = sf[1];
+            A2 = sf[2] * (dt / kFourPi);
+        }
         const double Tm = T[x.c];
         const double B4 = A2 * aa * G.a_rad;
         const double B1 = rh * G.cv * (1.0 - A2 * as);
@@ -115,10 +119,14 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
             if (beam_cell && n == G.beam_angle) out = Real(G.beam_I);
             Iout[x.c * N + n] = out;
         }
-        M0 = wave_sum(M0);
-        M1 = wave_sum(M1);
-        M2 = wave_sum(M2);
-        M3 = wave_sum(M3);
+        {
+            double sm[4] = {M0, M1, M2, M3};
+            group_sum_v<kWave, 4>(sm);
+            M0 = sm[0];
+            M1 = sm[1];
+            M2 = sm[2];
+            M3 = sm[3];
+        }
         if (lane == 0) {
             T[x.c] = Tp;
             nr_acc += bad;
@@ -217,8 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(DevGrid G, const Real *__res
         s[8] += w * y * z;
         s[9] += w * z * z;
     }
-#pragma unroll
-    for (int m = 0; m < 10; ++m) s[m] = wave_sum(s[m]);
+    group_sum_v<kWave, 10>(s);
     if (lane != 0) return;
     if (R)
         for (int m = 0; m < 10; ++m) R[10 * c + m] = s[m];
