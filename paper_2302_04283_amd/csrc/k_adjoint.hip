@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         const double B1 = rh * G.cv * (1.0 - A2 * as);
         const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
         int bad = 0;
-        const double Tp = quartic_root_fast(B4, B1, B0, bad);
+        const double Tp = quartic_root_fast(B4, B1, B0, bad, Tm);
         const double Ep = Em - rh * G.cv * (Tp - Tm);
         const double Tp3 = Tp * Tp * Tp;
         const double S = aa * G.a_rad * Tp3 * Tp + as * Ep;

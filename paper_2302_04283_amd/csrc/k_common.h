@@ -170,9 +170,12 @@ __device__ __forceinline__ double quartic_root(double B4, double B1, double B0, 
 
 // Same root, fewer instructions: Newton steps use a refined reciprocal, and
 // the fourth-root bound starts from an FP32 estimate enlarged by 1e-5 (still
-// an upper bound, so the iteration stays monotone).  Agrees with
-// quartic_root to a few ulp.
-__device__ __forceinline__ double quartic_root_fast(double B4, double B1, double B0, int &bad) {
+// an upper bound, so the iteration stays monotone).  A hint (the gas
+// temperature before the step) replaces the start when it is a smaller upper
+// bound (P(hint) >= 0), which saves iterations when the coupling moves T
+// little.  Agrees with quartic_root to a few ulp.
+__device__ __forceinline__ double quartic_root_fast(double B4, double B1, double B0, int &bad,
+                                                    double hint = 0.0) {
     bad = 0;
     if (!(isfinite(B4) && isfinite(B1) && isfinite(B0)) || !(B0 < 0.0) || !(B1 > 0.0)) {
         bad = 1;
@@ -185,6 +188,10 @@ __device__ __forceinline__ double quartic_root_fast(double B4, double B1, double
     if (x < 1e30 && x > 1e-30) {
         const float q = sqrtf(sqrtf((float)x)) * 1.00001f;
         T = fmin(lin, (double)q);
+    }
+    if (hint > 0.0 && hint < T) {
+        const double h3 = hint * hint * hint;
+        if (fma(B4 * h3, hint, fma(B1, hint, B0)) >= 0.0) T = hint;
     }
     for (int it = 0; it < 200; ++it) {
         const double T3 = T * T * T;

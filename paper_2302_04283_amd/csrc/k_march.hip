@@ -390,43 +390,45 @@ void k_march(
         const double B1 = rh * G.cv * (1.0 - A2 * as);
         const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
         int bad = 0;
-        const double Tp = quartic_root_fast(B4, B1, B0, bad);
+        const double Tp = quartic_root_fast(B4, B1, B0, bad, Tm);
         const double Ep = Em - rh * G.cv * (Tp - Tm);
         const double Tp2 = Tp * Tp;
         const double S = aa * G.a_rad * Tp2 * Tp2 + as * Ep;
         const Real cS = Real(dt * S / kFourPi);
         const bool beam_cell = G.beam != nullptr && G.beam[cidx];
-        double Mv0 = 0.0, Mv1 = 0.0, Mv2 = 0.0, Mv3 = 0.0;
         Real *dst = Iout + cidx * N;
+        Real Ipv[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int n = a + SW * k;
             const Real Ip = fma(kk[k], Is[k], cS * gg[k]);
-            const double dI = (double)(Ip - Is[k]) * s_dom[n];
-            Mv0 += dI;
-            Mv1 = fma(dI, s_nh[n], Mv1);
-            Mv2 = fma(dI, s_nh[NP + n], Mv2);
-            Mv3 = fma(dI, s_nh[2 * NP + n], Mv3);
+            Ipv[k] = Ip;
             Real out = fm[k] ? Real(0) : Ip;
             out = (beam_cell && n == G.beam_angle) ? Real(G.beam_I) : out;
             if (k < NC - 1 || n < N) dst[n] = out;
         }
-        {
-            double sm[4] = {Mv0, Mv1, Mv2, Mv3};
-            group_sum_v<SW, 4>(sm);
-            Mv0 = sm[0];
-            Mv1 = sm[1];
-            Mv2 = sm[2];
-            Mv3 = sm[3];
-        }
         if (a == 0) {
             T[cidx] = Tp;
             nr_acc += bad;
-            if (dT0) {
+        }
+        if (dT0) {
+            // four-momentum handed to the gas: -n^0 E0 . sum (I+ - I*) (1, n) dOmega
+            double sm[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const int n = a + SW * k;
+                const double dI = (double)(Ipv[k] - Is[k]) * s_dom[n];
+                sm[0] += dI;
+                sm[1] = fma(dI, s_nh[n], sm[1]);
+                sm[2] = fma(dI, s_nh[NP + n], sm[2]);
+                sm[3] = fma(dI, s_nh[2 * NP + n], sm[3]);
+            }
+            group_sum_v<SW, 4>(sm);
+            if (a == 0) {
 #pragma unroll
                 for (int al = 0; al < 4; ++al)
-                    dT0[4 * cidx + al] -= n0u * (E0[4 * al] * Mv0 + E0[4 * al + 1] * Mv1 +
-                                                 E0[4 * al + 2] * Mv2 + E0[4 * al + 3] * Mv3);
+                    dT0[4 * cidx + al] -= n0u * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
+                                                 E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
             }
         }
         // single buffer: every group must be done reading plane z first.
