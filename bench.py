@@ -33,9 +33,8 @@ def _upload_initial(prob, dtype, dev):
     import numpy as np
     import torch
     out = torch.empty((prob.n[2], prob.n[1], prob.n[0], prob.nang), dtype=dtype, device=dev)
-    for k in range(0, prob.n[2], 8):
-        kr = (k, min(prob.n[2], k + 8))
-        out[kr[0]:kr[1]] = torch.as_tensor(prob.initial_intensity(np.float64, kr)).to(dev, dtype)
+    for kr, arr in prob.initial_intensity_slabs(np.float64):
+        out[kr[0]:kr[1]] = torch.as_tensor(arr).to(dev, dtype)
     return out
 
 
@@ -128,6 +127,25 @@ def time_fwd_adjoint(prob, precision, steps, ckpt, dt, dev):
     return wall, finite
 
 
+def copy_bandwidth(dev, nbytes=1 << 30, reps=5):
+    """Achieved bandwidth of a plain device-to-device copy (read + write)."""
+    import torch
+    a = torch.ones(nbytes // 4, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize(dev)
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / sec / 1e9
+
+
 def cpu_baseline(seconds):
     import torch
     from oracle import step as O
@@ -167,6 +185,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--checkpoint-every", type=int, default=10)
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the copy-bandwidth and 42/92-direction context rows")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference for scaling HBM byte counters)")
@@ -231,7 +251,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": _traffic(bytes_launch),
-                     "kernel": "k_step (fused transport + coupling)",
+                     "kernel": "k_march<float, 32, 6> (fused tiled step: transport + coupling "
+                               "+ bookkeeping), timed with its finaliser",
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "avg_launch_s": avg},
         "no_root_events": st32["no_root"],
@@ -245,15 +266,35 @@ def main():
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * wall64 / K,
                        "achieved_GBs": b64 / avg64 / 1e9, "speedup_fp32_over_fp64": value / v64}
     if not args.no_adjoint:
-        wall_fa, finite = time_fwd_adjoint(prob, rt.RT_F32, K, args.checkpoint_every, dt, dev)
-        print("[bench] fwd+adjoint done: %.3f ms/step" % (1e3 * wall_fa / K), file=sys.stderr,
-              flush=True)
-        out["fwd_adjoint"] = {"value": ncell * nang * K / wall_fa, "unit": "cell-angle updates/s",
-                              "ms_per_step": 1e3 * wall_fa / K,
-                              "checkpoint_every": args.checkpoint_every,
-                              "gradients_finite": finite,
-                              "functional": "luminosity through the upper x face; gradients "
-                                            "wrt kappa_a and T0"}
+        precs = [(rt.RT_F32, "fwd_adjoint")] + ([] if args.no_fp64 else [(rt.RT_F64, "fwd_adjoint_fp64")])
+        for prec, key in precs:
+            wall_fa, finite = time_fwd_adjoint(prob, prec, K, args.checkpoint_every, dt, dev)
+            print("[bench] %s done: %.3f ms/step" % (key, 1e3 * wall_fa / K), file=sys.stderr,
+                  flush=True)
+            out[key] = {"value": ncell * nang * K / wall_fa, "unit": "cell-angle updates/s",
+                        "ms_per_step": 1e3 * wall_fa / K,
+                        "checkpoint_every": args.checkpoint_every,
+                        "gradients_finite": finite,
+                        "functional": "luminosity through the upper x face; gradients "
+                                      "wrt kappa_a, kappa_s, T0 and I0"}
+        if "fwd_adjoint_fp64" in out:
+            out["fwd_adjoint"]["speedup_fp32_over_fp64"] = (out["fwd_adjoint"]["value"] /
+                                                            out["fwd_adjoint_fp64"]["value"])
+    if not args.no_context:
+        # a plain device-to-device copy (the STREAM-like ceiling) and the
+        # paper's GPU benchmark angle counts on the same 128^3 grid
+        out["copy_GBs"] = copy_bandwidth(dev)
+        shapes = {}
+        for lev in (2, 3):
+            p2 = W.make_problem(CONFIG, nlev=lev)
+            g2 = rt.Grid(p2, rt.RT_F32)
+            dt2 = g2.max_dt(p2.cfl)
+            g2.close()
+            w2, _, _ = time_path(p2, rt.RT_F32, 20, 3, dt2, dev)
+            shapes["%d directions" % p2.nang] = {"value": p2.ncell * p2.nang * 20 / w2,
+                                                  "ms_per_step": 1e3 * w2 / 20}
+        out["paper_shapes_fp32"] = shapes
+        print("[bench] context done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)

@@ -49,9 +49,41 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     const Real dtR = Real(dt);
     double dummy_l = 0.0, dummy_m = 0.0;
     const bool uniform_geo = G.g0 == 1 && G.g1 == 1 && G.g2 == 1;
+    // per-cell inputs of the stored-I* variant, prefetched one cell ahead
+    // (the loads of the next cell are in flight while this one is computed)
+    struct In {
+        Real I[NCH], lp[NCH];
+        double u1, u2, u3, rho, ka, ks, T, lT;
+    };
+    auto fetch = [&](long long c, In &v) {
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = min(lane + SW * ch, N - 1);
+            v.I[ch] = Istar[c * N + n];
+            v.lp[ch] = lamI1[c * N + n];
+        }
+        v.u1 = uvec[3 * c];
+        v.u2 = uvec[3 * c + 1];
+        v.u3 = uvec[3 * c + 2];
+        v.rho = rho[c];
+        v.ka = kap_a[c];
+        v.ks = kap_s[c];
+        v.T = Tin[c];
+        v.lT = lamT1[c];
+    };
+    In cur{}, nxt{};
+    {
+        const long long c0 = (long long)blockIdx.x * kCellsPerBlock + grp;
+        if constexpr (!RECOMP)
+            if (c0 < ncell) fetch(c0, cur);
+    }
     for (int cw = grp; cw < kCellsPerBlock; cw += kGroups) {
         const long long cc = (long long)blockIdx.x * kCellsPerBlock + cw;
         if (cc >= ncell) break;
+        if constexpr (!RECOMP) {
+            const long long cn = cc + kGroups;
+            if (cw + kGroups < kCellsPerBlock && cn < ncell) fetch(cn, nxt);
+        }
         Cell x;
         if constexpr (RECOMP) {
             x = make_cell(G, cc);
@@ -70,55 +102,58 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
                        (G.g0 > 1 ? x.i : 0);
             }
         }
+        if constexpr (RECOMP) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = min(lane + SW * ch, N - 1);
+                cur.I[ch] = transport_dir(G, Iin, x, n, dtR, invV[x.gc], dummy_l, dummy_m);
+                cur.lp[ch] = lamI1[x.c * N + n];
+            }
+            cur.u1 = uvec[3 * x.c];
+            cur.u2 = uvec[3 * x.c + 1];
+            cur.u3 = uvec[3 * x.c + 2];
+            cur.rho = rho[x.c];
+            cur.ka = kap_a[x.c];
+            cur.ks = kap_s[x.c];
+            cur.T = Tin[x.c];
+            cur.lT = lamT1[x.c];
+        }
         Real Is[NCH];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const int n = lane + SW * ch;
-            Is[ch] = Real(0);
-            if (n >= N) continue;
-            // I* as stored by the forward step, or recomputed
-            if constexpr (RECOMP)
-                Is[ch] = transport_dir(G, Iin, x, n, dtR, invV[x.gc], dummy_l, dummy_m);
-            else
-                Is[ch] = Istar[x.c * N + n];
-        }
+        for (int ch = 0; ch < NCH; ++ch) Is[ch] = lane + SW * ch < N ? cur.I[ch] : Real(0);
         // forward coupling, recomputed.  Per direction: nb = n^0bar (fluid
         // frame), dn = n^0 + nb (alpha_a + alpha_s) dt, rr = 1/(nb^2 dn) and
-        // from it idn = 1/dn, k = n^0/dn, r1 = 1/(nb dn); w = nb^2 dOmega
-        const double u1 = uvec[3 * x.c], u2 = uvec[3 * x.c + 1], u3 = uvec[3 * x.c + 2];
+        // from it idn = 1/dn, k = n^0/dn, 1/(nb dn) = nb rr; w = nb^2 dOmega.
+        // Only nb and rr are kept per direction (registers); the rest is
+        // re-formed where it is used.
+        const double u1 = cur.u1, u2 = cur.u2, u3 = cur.u3;
         const double u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
-        const double rh = rho[x.c];
-        const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh;
+        const double rh = cur.rho;
+        const double aa = cur.ka * rh, as = cur.ks * rh;
         const double tau = (aa + as) * dt;
         const double n0 = G.n0u[x.gc];
-        double nbv[NCH], dnv[NCH], rrv[NCH], idnv[NCH], kv[NCH], wv[NCH], Iv[NCH], dom[NCH];
+        double nbv[NCH], rrv[NCH];
+        bool live[NCH];
         double sf[3] = {0.0, 0.0, 0.0};   // Em, A1, A2
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + SW * ch;
-            const bool live = n < N && !G.mask[(size_t)x.gc * N + (n < N ? n : 0)];
-            const int m = live ? n : 0;
+            live[ch] = n < N && !G.mask[(size_t)x.gc * N + (n < N ? n : 0)];
+            const int m = live[ch] ? n : 0;
             const double nb = u0 - fma(u1, G.nhat[3 * m], fma(u2, G.nhat[3 * m + 1], u3 * G.nhat[3 * m + 2]));
             const double nb2 = nb * nb;
-            const double dn = fma(nb, tau, n0);
-            const double rr = rcp64(nb2 * dn);
-            const double idn = nb2 * rr;
-            dom[ch] = live ? G.domega[m] : 0.0;   // zero weight: masked or padding
+            const double rr = rcp64(nb2 * fma(nb, tau, n0));
             nbv[ch] = nb;
-            dnv[ch] = dn;
             rrv[ch] = rr;
-            idnv[ch] = idn;
-            kv[ch] = n0 * idn;
-            wv[ch] = nb2 * dom[ch];
-            Iv[ch] = (double)Is[ch];
-            const double Iw = Iv[ch] * wv[ch];
+            const double dom = live[ch] ? G.domega[m] : 0.0;   // zero weight: masked or padding
+            const double Iw = (double)Is[ch] * (nb2 * dom);
             sf[0] += Iw;
-            sf[1] = fma(kv[ch], Iw, sf[1]);
-            sf[2] = fma(dom[ch], nb * rr, sf[2]);
+            sf[1] = fma(n0 * nb2 * rr, Iw, sf[1]);
+            sf[2] = fma(dom, nb * rr, sf[2]);
         }
         group_sum_v<SW, 3>(sf);
         const double Em = sf[0], A1 = sf[1], A2 = sf[2] * (dt / kFourPi);
-        const double Tm = Tin[x.c];
+        const double Tm = cur.T;
         const double B4 = A2 * aa * G.a_rad;
         const double B1 = rh * G.cv * (1.0 - A2 * as);
         const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
@@ -132,27 +167,35 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         const bool beam_cell = G.beam != nullptr && G.beam[x.c];
         const double c4 = dt / kFourPi;
         double sr[4] = {0.0, 0.0, 0.0, 0.0};
-        double lpv[NCH];
+        Real lpv[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + SW * ch;
-            const double nb = nbv[ch], rr = rrv[ch], idn = idnv[ch], k = kv[ch];
-            const double gdir = c4 * (nb * rr) * rr * dnv[ch];   // dt/(4 pi dn nb^3)
+            const int m = live[ch] ? n : 0;
+            const double nb = nbv[ch], rr = rrv[ch];
+            const double nb2 = nb * nb;
+            const double dn = fma(nb, tau, n0);
+            const double idn = nb2 * rr;                          // 1/dn
+            const double k = n0 * idn;                            // n^0/dn
+            const double dom = live[ch] ? G.domega[m] : 0.0;
+            const double I = (double)Is[ch];
+            const double gdir = c4 * (nb * rr) * rr * dn;         // dt/(4 pi dn nb^3)
             const double nbdn = nb * idn;                         // nb/dn
-            const bool use = n < N && dom[ch] != 0.0 && !(beam_cell && n == G.beam_angle);
-            const double lp = use ? (double)lamI1[x.c * N + n] : 0.0;
-            lpv[ch] = lp;
+            const bool use = live[ch] && !(beam_cell && n == G.beam_angle);
+            const Real lpr = use ? cur.lp[ch] : Real(0);
+            lpv[ch] = lpr;
+            const double lp = (double)lpr;
             sr[0] = fma(lp, gdir, sr[0]);
-            sr[1] = fma(lp * fma(Iv[ch], k, S * gdir), nbdn, sr[1]);
-            sr[2] = fma(wv[ch] * Iv[ch] * k, nbdn, sr[2]);
-            sr[3] = fma(dom[ch] * idn, idn, sr[3]);
+            sr[1] = fma(lp * fma(I, k, S * gdir), nbdn, sr[1]);
+            sr[2] = fma(nb2 * dom * I * k, nbdn, sr[2]);
+            sr[3] = fma(dom * idn, idn, sr[3]);
         }
         group_sum_v<SW, 4>(sr);
         const double lS = sr[0], X1 = sr[1], X2 = sr[2], X3 = sr[3];
         // scalar reverse of S, Ep, the quartic and the B coefficients
         const double rcv = rh * G.cv;
         const double lEp = lS * as;
-        const double lTp = lamT1[x.c] + lS * 4.0 * aa * G.a_rad * Tp3 - rcv * lEp;
+        const double lTp = cur.lT + lS * 4.0 * aa * G.a_rad * Tp3 - rcv * lEp;
         double lTm = rcv * lEp;
         double laa = lS * G.a_rad * Tp3 * Tp;
         double las = lS * Ep;
@@ -179,9 +222,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
             const int n = lane + SW * ch;
             if (n >= N) continue;
             Real out = Real(0);
-            if (dom[ch] != 0.0) {
-                const double k = kv[ch];
-                const double lstar = fma(k, lpv[ch], fma(lA1, k, lEm) * wv[ch]);
+            if (live[ch]) {
+                const double nb = nbv[ch];
+                const double nb2 = nb * nb;
+                const double k = n0 * nb2 * rrv[ch];
+                const double w = nb2 * G.domega[n];
+                const double lstar = fma(k, (double)lpv[ch], fma(lA1, k, lEm) * w);
                 out = Real(lstar * rcp64((double)q[(size_t)x.gc * N + n]));
             }
             psi[x.c * N + n] = out;
@@ -191,6 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
             if (gka) gka[x.c] += laa * rh;
             if (gks) gks[x.c] += las * rh;
         }
+        if constexpr (!RECOMP) cur = nxt;
     }
 }
 
@@ -323,11 +370,11 @@ int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
     const Real *in = static_cast<const Real *>(Iin);
     const Real *l1 = static_cast<const Real *>(lamI1);
     Real *psi = static_cast<Real *>(work);
-    // lanes per cell: 16 for small angle sets, else a full wavefront (fewer
-    // directions per lane keep the per-direction state in registers; the
-    // per-cell work is then spread over the fewest cells per wavefront)
+    // lanes per cell: the narrowest group (fewest lanes repeating the
+    // per-cell work) whose directions-per-lane, at most 11, keep the
+    // per-direction state and the prefetched next cell in registers
     const int N = G.nang;
-    int sw = N <= 96 ? 16 : 64;
+    int sw = N <= 176 ? 16 : (N <= 352 ? 32 : 64);
     int cnc = (N + sw - 1) / sw;
 #define RT_LAUNCH(SW, NC, RC)                                                                  \
     if (sw == SW && cnc == NC)                                                                 \
@@ -338,9 +385,12 @@ int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
     if (Istar) {
         RT_LAUNCH(16, 1, false) RT_LAUNCH(16, 2, false) RT_LAUNCH(16, 3, false)
         RT_LAUNCH(16, 4, false) RT_LAUNCH(16, 5, false) RT_LAUNCH(16, 6, false)
-        RT_LAUNCH(64, 2, false) RT_LAUNCH(64, 3, false) RT_LAUNCH(64, 4, false)
-        RT_LAUNCH(64, 5, false) RT_LAUNCH(64, 6, false)
-        RT_LAUNCH(64, 7, false) RT_LAUNCH(64, 8, false)
+        RT_LAUNCH(16, 7, false) RT_LAUNCH(16, 8, false) RT_LAUNCH(16, 9, false)
+        RT_LAUNCH(16, 10, false) RT_LAUNCH(16, 11, false)
+        RT_LAUNCH(32, 6, false) RT_LAUNCH(32, 7, false) RT_LAUNCH(32, 8, false)
+        RT_LAUNCH(32, 9, false) RT_LAUNCH(32, 10, false) RT_LAUNCH(32, 11, false)
+        RT_LAUNCH(64, 6, false) RT_LAUNCH(64, 7, false) RT_LAUNCH(64, 8, false)
+        RT_LAUNCH(64, 9, false) RT_LAUNCH(64, 10, false) RT_LAUNCH(64, 11, false)
         return RT_EINVAL;
     } else {
         // the recompute carries the transport's registers: one cell per wavefront

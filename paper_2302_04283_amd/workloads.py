@@ -231,6 +231,19 @@ class Problem:
         base = self.a_rad * T ** 4 / (4.0 * math.pi)
         return (base[..., None] * (1.0 + 0.1 * xi)).astype(dtype)
 
+    def initial_intensity_slabs(self, dtype=np.float64, slab=8, workers=8):
+        """The same field as ``initial_intensity``, generated as axis-2 slabs
+        of ``slab`` planes on a thread pool (numpy releases the GIL) and
+        yielded in order as ((k0, k1), array): full-size grids without one
+        multi-GB host array."""
+        from concurrent.futures import ThreadPoolExecutor
+        ranges = [(k, min(self.n[2], k + slab)) for k in range(0, self.n[2], slab)]
+        with ThreadPoolExecutor(max(1, workers)) as ex:
+            for i in range(0, len(ranges), max(1, workers)):
+                part = ranges[i:i + max(1, workers)]
+                for kr, arr in zip(part, ex.map(lambda r: self.initial_intensity(dtype, r), part)):
+                    yield kr, arr
+
 
 # ----------------------------------------------------------------------------
 # geometry builders

@@ -43,7 +43,7 @@ def _max_rel(a, b):
 
 
 @pytest.mark.parametrize("cfg,scale,steps,K", [("c4", (12, 8, 6), 6, 4), ("c3", (10, 8, 4), 4, 2),
-                                               ("c2", (8, 8, 8), 5, 2)])
+                                               ("c2", (8, 8, 8), 5, 2), ("c5", (6, 4, 4), 3, 2)])
 @pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
 def test_adjoint_matches_reference_gradient(cfg, scale, steps, K, prec):
     p = W.make_problem(cfg, scale=scale)

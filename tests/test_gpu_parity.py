@@ -157,10 +157,8 @@ def test_invalid_arguments_raise():
 # ------------------------------------------------------------ full-size cases
 def _upload_initial(prob, dtype, dev):
     out = torch.empty((prob.n[2], prob.n[1], prob.n[0], prob.nang), dtype=dtype, device=dev)
-    step = 8
-    for k in range(0, prob.n[2], step):
-        kr = (k, min(prob.n[2], k + step))
-        out[kr[0]:kr[1]] = torch.as_tensor(prob.initial_intensity(np.float64, kr)).to(dev, dtype)
+    for kr, arr in prob.initial_intensity_slabs(np.float64):
+        out[kr[0]:kr[1]] = torch.as_tensor(arr).to(dev, dtype)
     return out
 
 
@@ -208,6 +206,14 @@ def test_c2_full_size_fp64_subbox():
 def test_c3_full_size_fp32_subbox():
     _full_vs_subbox("c3", rt.RT_F32, 2, (50, 24, -8), 12, F32_I, F32_T,
                     "c3 full 128x64x128 fp32 2 steps, block 12^3")
+
+
+def test_c5_full_size_fp32_subbox():
+    # 256x128x256 x 362 directions (3.0e9 cell-directions, 12 GB per FP32
+    # state); the 12^3 block sits in the optically thick torus (r ~ 12,
+    # theta ~ pi/2) where tau_s reaches 100
+    _full_vs_subbox("c5", rt.RT_F32, 2, (150, 58, 10), 12, F32_I, F32_T,
+                    "c5 full 256x128x256x362 fp32 2 steps, torus block 12^3")
 
 
 # ------------------------------------------------------------ tiled fast path
