@@ -170,10 +170,11 @@ __device__ __forceinline__ double quartic_root(double B4, double B1, double B0, 
 
 // Same root, fewer instructions: Newton steps use a refined reciprocal, and
 // the fourth-root bound starts from an FP32 estimate enlarged by 1e-5 (still
-// an upper bound, so the iteration stays monotone).  A hint (the gas
-// temperature before the step) replaces the start when it is a smaller upper
-// bound (P(hint) >= 0), which saves iterations when the coupling moves T
-// little.  Agrees with quartic_root to a few ulp.
+// an upper bound, so the iteration stays monotone).  A hint h (the gas
+// temperature before the step) gives a closer upper bound: h itself when
+// P(h) >= 0, else one Newton step from h, which lands above the root because
+// P is convex and increasing on T >= 0; the smaller of that and the bound
+// above starts the iteration.  Agrees with quartic_root to a few ulp.
 __device__ __forceinline__ double quartic_root_fast(double B4, double B1, double B0, int &bad,
                                                     double hint = 0.0) {
     bad = 0;
@@ -191,7 +192,9 @@ __device__ __forceinline__ double quartic_root_fast(double B4, double B1, double
     }
     if (hint > 0.0 && hint < T) {
         const double h3 = hint * hint * hint;
-        if (fma(B4 * h3, hint, fma(B1, hint, B0)) >= 0.0) T = hint;
+        const double ph = fma(B4 * h3, hint, fma(B1, hint, B0));
+        const double th = ph >= 0.0 ? hint : hint - ph * rcp64(fma(4.0 * B4, h3, B1));
+        T = fmin(T, th);
     }
     for (int it = 0; it < 200; ++it) {
         const double T3 = T * T * T;
