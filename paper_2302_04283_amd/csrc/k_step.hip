@@ -52,13 +52,57 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
 
         Real Is[NCH];
         // ---------------------------------------------------------- transport
+        // axis by axis (one axis's rows live at a time), every direction of
+        // the lane; then angular fluxes, primitives and the mask
+        const Real *own = Iin + x.c * N;
+        Real dq[NCH];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const int n = lane + kWave * ch;
-            Is[ch] = Real(0);
-            if (n >= N) continue;
-            Is[ch] = transport_dir(G, Iin, x, n, dtR, ivol, lum_acc, me_acc);
-            if (Istar) Istar[x.c * N + n] = Is[ch];
+        for (int ch = 0; ch < NCH; ++ch) dq[ch] = Real(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            AxisRows<Real> R;
+            axis_rows(G, Iin, x, a, R);
+            if (R.ghost) {
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int n = lane + kWave * ch;
+                    if (n < N) dq[ch] += axis_div<true>(G, R, own[n], n, lum_acc);
+                }
+            } else {
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int n = lane + kWave * ch;
+                    if (n < N) dq[ch] += axis_div<false>(G, R, own[n], n, lum_acc);
+                }
+            }
+        }
+        {
+            const Real *qrow = q + (size_t)x.gc * N;
+            const uint8_t *mrow = G.mask + (size_t)x.gc * N;
+            const Real *vwrow = vw + (size_t)x.gc * G.nedge * 2;
+            const double volD = G.volD[x.gc];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                Is[ch] = Real(0);
+                if (n >= N) continue;
+                const Real Ic = own[n];
+                const Real div = G.has_edges ? angular_div(G, own, vwrow, n) : Real(0);
+                const Real qn = qrow[n];
+                const Real Qs = qn * Ic - dtR * ivol * dq[ch] - dtR * div / Real(G.domega[n]);
+                if (mrow[n]) {
+                    me_acc -= volD * G.domega[n] * (double)Qs;
+                    continue;
+                }
+                Is[ch] = Qs / qn;
+            }
+        }
+        if (Istar) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                if (n < N) Istar[x.c * N + n] = Is[ch];
+            }
         }
 
         // ---------------------------------------------------------- coupling

@@ -136,4 +136,116 @@ __device__ __forceinline__ Real transport_dir(const DevGrid &G, const Real *__re
     return Qs / qn;
 }
 
+// Row pointers of one axis for the general step: the cell is uniform across
+// the wavefront, so its neighbour rows and face geometry rows are resolved
+// once per cell and axis (boundary conditions included); each direction then
+// loads row[n], one lane offset shared by all loads of a direction.
+template <typename Real>
+struct AxisRows {
+    const Real *nb[4];            // rows at offsets -2, -1, +1, +2
+    const int8_t *bs[4];          // outflow ghost: sign row of the boundary face, else nullptr
+    const Real *Clo, *Chi;        // face coefficients of the lower/upper face
+    const int8_t *Slo, *Shi;
+    bool ghost;                   // some offset lands on an outflow/vacuum ghost
+    bool lum_lo, lum_hi;          // lower/upper face is the luminosity face
+};
+
+template <typename Real>
+__device__ __forceinline__ void axis_rows(const DevGrid &G, const Real *__restrict__ Iin,
+                                          const Cell &x, int a, AxisRows<Real> &R) {
+    const int N = G.nang;
+    const int coord = axis_coord(x, a);
+    const int len = axis_len(G, a);
+    const long long stride = axis_stride(G, a);
+    R.ghost = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int o = k < 2 ? k - 2 : k - 1;
+        const int idx = coord + o;
+        R.bs[k] = nullptr;
+        if (idx >= 0 && idx < len) {
+            R.nb[k] = Iin + (x.c + (long long)o * stride) * N;
+        } else {
+            const int side = idx < 0 ? 0 : 1;
+            if (G.bc[a][side] == RT_BC_PERIODIC) {
+                const int w = ((idx % len) + len) % len;
+                R.nb[k] = Iin + (x.c + (long long)(w - coord) * stride) * N;
+            } else {
+                const int edge = side ? len - 1 : 0;
+                R.nb[k] = Iin + (x.c + (long long)(edge - coord) * stride) * N;
+                R.bs[k] = G.sgn[a] + (size_t)face_geo(G, a, side ? len : 0, x) * N;
+                R.ghost = true;
+            }
+        }
+    }
+    const int flo = face_geo(G, a, coord, x), fhi = face_geo(G, a, coord + 1, x);
+    R.Clo = static_cast<const Real *>(G.C[a]) + (size_t)flo * N;
+    R.Chi = static_cast<const Real *>(G.C[a]) + (size_t)fhi * N;
+    R.Slo = G.sgn[a] + (size_t)flo * N;
+    R.Shi = G.sgn[a] + (size_t)fhi * N;
+    R.lum_lo = a == G.lum_axis && G.lum_side == 0 && coord == 0;
+    R.lum_hi = a == G.lum_axis && G.lum_side == 1 && coord == len - 1;
+}
+
+// Contribution of one axis to the flux divergence of direction n (the same
+// arithmetic as transport_dir, so the same I* bit for bit).  GHOST: some
+// neighbour along this axis is an outflow/vacuum ghost.
+template <bool GHOST, typename Real>
+__device__ __forceinline__ Real axis_div(const DevGrid &G, const AxisRows<Real> &R, Real Ic, int n,
+                                         double &lum_acc) {
+    Real v[5];
+    v[2] = Ic;
+    const bool plm = G.recon == RT_RECON_PLM;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int slot = k < 2 ? k : k + 1;
+        if ((k == 0 || k == 3) && !plm) {
+            v[slot] = Real(0);
+            continue;
+        }
+        Real val = R.nb[k][n];
+        if constexpr (GHOST) {
+            if (R.bs[k] != nullptr) {
+                // ghost beyond a lower (k < 2) or upper face: the edge cell
+                // for directions leaving through it, else zero
+                const int s = R.bs[k][n];
+                const bool out = k < 2 ? (s < 0) : (s > 0);
+                val = out ? val : Real(0);
+            }
+        }
+        v[slot] = val;
+    }
+    Real dlm = Real(0), dl0 = Real(0), dlp = Real(0);
+    if (plm) {
+        dlm = van_leer(v[1] - v[0], v[2] - v[1]);
+        dl0 = van_leer(v[2] - v[1], v[3] - v[2]);
+        dlp = van_leer(v[3] - v[2], v[4] - v[3]);
+    }
+    const int slo = R.Slo[n], shi = R.Shi[n];
+    const Real ulo = slo > 0 ? v[1] + Real(0.5) * dlm : (slo < 0 ? v[2] - Real(0.5) * dl0 : Real(0));
+    const Real uhi = shi > 0 ? v[2] + Real(0.5) * dl0 : (shi < 0 ? v[3] - Real(0.5) * dlp : Real(0));
+    const Real Flo = R.Clo[n] * ulo;
+    const Real Fhi = R.Chi[n] * uhi;
+    if (R.lum_hi) lum_acc -= G.domega[n] * (double)Fhi;
+    if (R.lum_lo) lum_acc += G.domega[n] * (double)Flo;
+    return Fhi - Flo;
+}
+
+// Angular-flux divergence of direction n within the cell's own row.
+template <typename Real>
+__device__ __forceinline__ Real angular_div(const DevGrid &G, const Real *__restrict__ own,
+                                            const Real *__restrict__ vwrow, int n) {
+    Real div = Real(0);
+#pragma unroll
+    for (int s = 0; s < kMaxNbr; ++s) {
+        const int e = G.adj_e[n * kMaxNbr + s];
+        if (e < 0) break;
+        const Real vv = vwrow[2 * e], ww = vwrow[2 * e + 1];
+        const Real up = vv > Real(0) ? own[G.edge_lo[e]] : (vv < Real(0) ? own[G.edge_hi[e]] : Real(0));
+        const Real F = ww * up;
+        div += G.adj_s[n * kMaxNbr + s] > 0 ? F : -F;
+    }
+    return div;
+}
+
 }  // namespace rt
