@@ -43,6 +43,12 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
     const Real dtR = Real(dt);
     double lum_acc = 0.0, me_acc = 0.0;
     int nr_acc = 0;
+    // angular-edge records of every direction, staged once per workgroup
+    __shared__ int s_adj[kMaxAngGeneral * kMaxNbr];
+    if (G.has_edges) {
+        for (int i = threadIdx.x; i < N * kMaxNbr; i += kBlock) s_adj[i] = edge_record(G, i);
+        __syncthreads();
+    }
 
     for (int cw = wave; cw < kCellsPerBlock; cw += kWavesPerBlock) {
         const long long cc = (long long)blockIdx.x * kCellsPerBlock + cw;
@@ -87,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                 Is[ch] = Real(0);
                 if (n >= N) continue;
                 const Real Ic = own[n];
-                const Real div = G.has_edges ? angular_div(G, own, vwrow, n) : Real(0);
+                const Real div = G.has_edges ? angular_div_rec(s_adj, own, vwrow, n) : Real(0);
                 const Real qn = qrow[n];
                 const Real Qs = qn * Ic - dtR * ivol * dq[ch] - dtR * div / Real(G.domega[n]);
                 if (mrow[n]) {
@@ -106,80 +112,81 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
         }
 
         // ---------------------------------------------------------- coupling
+        // per direction nb = n^0bar, dn = n^0 + nb tau, rr = 1/(nb^2 dn); the
+        // quotients n^0/dn, 1/(nb dn), 1/(dn nb^3) are products with rr
         const double u1 = uvec[3 * x.c], u2 = uvec[3 * x.c + 1], u3 = uvec[3 * x.c + 2];
-        const double u0 = sqrt(1.0 + u1 * u1 + u2 * u2 + u3 * u3);
+        const double u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
         const double rh = rho[x.c];
-        const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh, aE = aa + as;
+        const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh;
+        const double tau = (aa + as) * dt;
         const double n0 = G.n0u[x.gc];
-        double Em = 0.0, A1 = 0.0, A2 = 0.0;
+        const uint8_t *mrow = G.mask + (size_t)x.gc * N;
+        double nbv[NCH], rrv[NCH];
+        double sf[3] = {0.0, 0.0, 0.0};   // Em, A1, A2
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + kWave * ch;
-            if (n >= N || G.mask[(size_t)x.gc * N + n]) continue;
-            const double nb = u0 - (u1 * G.nhat[3 * n] + u2 * G.nhat[3 * n + 1] + u3 * G.nhat[3 * n + 2]);
-            const double dn = n0 + nb * aE * dt;
-            const double w2 = nb * nb * G.domega[n];
-            const double I = (double)Is[ch];
-            Em += I * w2;
-            A1 += (n0 / dn) * I * w2;
-            A2 += G.domega[n] / (nb * dn);
+            const int m = n < N ? n : 0;
+            const double nb = u0 - fma(u1, G.nhat[3 * m], fma(u2, G.nhat[3 * m + 1], u3 * G.nhat[3 * m + 2]));
+            const double nb2 = nb * nb;
+            const double rr = rcp64(nb2 * fma(nb, tau, n0));
+            nbv[ch] = nb;
+            rrv[ch] = rr;
+            if (n >= N || mrow[n]) continue;
+            const double dom = G.domega[n];
+            const double Iw = (double)Is[ch] * (nb2 * dom);
+            sf[0] += Iw;
+            sf[1] = fma(n0 * nb2 * rr, Iw, sf[1]);
+            sf[2] = fma(dom, nb * rr, sf[2]);
         }
-        {
-            double sf[3] = {Em, A1, A2};
-            group_sum_v<kWave, 3>(sf);
-            Em = sf[0];
-            A1 = sf[1];
-            A2 = sf[2] * (dt / kFourPi);
-        }
+        group_sum_v<kWave, 3>(sf);
+        const double Em = sf[0], A1 = sf[1], A2 = sf[2] * (dt / kFourPi);
         const double Tm = T[x.c];
         const double B4 = A2 * aa * G.a_rad;
         const double B1 = rh * G.cv * (1.0 - A2 * as);
         const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
         int bad = 0;
-        const double Tp = quartic_root(B4, B1, B0, bad);
+        const double Tp = quartic_root_fast(B4, B1, B0, bad, Tm);
         const double Ep = Em - rh * G.cv * (Tp - Tm);
         const double Tp2 = Tp * Tp;
         const double S = aa * G.a_rad * Tp2 * Tp2 + as * Ep;
-        double M0 = 0.0, M1 = 0.0, M2 = 0.0, M3 = 0.0;
+        const double cS = S * (dt / kFourPi);
+        double sm[4] = {0.0, 0.0, 0.0, 0.0};
         const bool beam_cell = G.beam != nullptr && G.beam[x.c];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + kWave * ch;
             if (n >= N) continue;
             Real out = Real(0);
-            if (!G.mask[(size_t)x.gc * N + n]) {
-                const double nx = G.nhat[3 * n], ny = G.nhat[3 * n + 1], nz = G.nhat[3 * n + 2];
-                const double nb = u0 - (u1 * nx + u2 * ny + u3 * nz);
-                const double dn = n0 + nb * aE * dt;
+            if (!mrow[n]) {
+                const double nb = nbv[ch], rr = rrv[ch];
+                const double nbrr = nb * rr;                       // 1/(nb dn)
+                const double dn = fma(nb, tau, n0);
                 const double I = (double)Is[ch];
-                const double Ip = (n0 / dn) * I + dt * S / (kFourPi * dn * nb * nb * nb);
+                // I+ = (n^0/dn) I* + dt S / (4 pi dn nb^3)
+                const double Ip = fma(n0 * nb * nbrr, I, cS * (nbrr * rr * dn));
                 const double dI = (Ip - I) * G.domega[n];
-                M0 += dI;
-                M1 += dI * nx;
-                M2 += dI * ny;
-                M3 += dI * nz;
+                sm[0] += dI;
+                sm[1] = fma(dI, G.nhat[3 * n], sm[1]);
+                sm[2] = fma(dI, G.nhat[3 * n + 1], sm[2]);
+                sm[3] = fma(dI, G.nhat[3 * n + 2], sm[3]);
                 out = Real(Ip);
             }
             if (beam_cell && n == G.beam_angle) out = Real(G.beam_I);
             Iout[x.c * N + n] = out;
         }
-        {
-            double sm[4] = {M0, M1, M2, M3};
-            group_sum_v<kWave, 4>(sm);
-            M0 = sm[0];
-            M1 = sm[1];
-            M2 = sm[2];
-            M3 = sm[3];
-        }
         if (lane == 0) {
             T[x.c] = Tp;
             nr_acc += bad;
-            if (dT0) {
+        }
+        if (dT0) {
+            group_sum_v<kWave, 4>(sm);
+            if (lane == 0) {
                 const double *E0 = G.E0 + 16 * x.gc;
 #pragma unroll
                 for (int al = 0; al < 4; ++al)
-                    dT0[4 * x.c + al] -= n0 * (E0[4 * al] * M0 + E0[4 * al + 1] * M1 +
-                                               E0[4 * al + 2] * M2 + E0[4 * al + 3] * M3);
+                    dT0[4 * x.c + al] -= n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
+                                               E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
             }
         }
     }

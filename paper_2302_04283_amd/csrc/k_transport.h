@@ -248,4 +248,40 @@ __device__ __forceinline__ Real angular_div(const DevGrid &G, const Real *__rest
     return div;
 }
 
+// Largest direction count of the general kernels (8 chunks of 64 lanes).
+constexpr int kMaxAngGeneral = 8 * kWave;
+
+// Edge record of slot s of direction n (i = n * kMaxNbr + s): the edge index
+// (bits 0-14), the direction across the edge (bits 15-29) and whether n is
+// the edge's lo end (bit 30); -1 where the polygon has no such edge.
+__device__ __forceinline__ int edge_record(const DevGrid &G, int i) {
+    const int e = G.adj_e[i];
+    if (e < 0) return -1;
+    const bool is_lo = G.adj_s[i] > 0;
+    const int m = is_lo ? G.edge_hi[e] : G.edge_lo[e];
+    return e | (m << 15) | ((is_lo ? 1 : 0) << 30);
+}
+
+// angular_div from staged edge records (the same arithmetic and order).
+template <typename Real>
+__device__ __forceinline__ Real angular_div_rec(const int *__restrict__ rec, const Real *__restrict__ own,
+                                                const Real *__restrict__ vwrow, int n) {
+    Real div = Real(0);
+    const Real In = own[n];
+#pragma unroll
+    for (int s = 0; s < kMaxNbr; ++s) {
+        const int r = rec[n * kMaxNbr + s];
+        if (r < 0) break;
+        const int e = r & 0x7fff, m = (r >> 15) & 0x7fff;
+        const bool is_lo = (r >> 30) & 1;
+        const Real vv = vwrow[2 * e], ww = vwrow[2 * e + 1];
+        const Real Im = own[m];
+        const Real Ilo = is_lo ? In : Im, Ihi = is_lo ? Im : In;
+        const Real up = vv > Real(0) ? Ilo : (vv < Real(0) ? Ihi : Real(0));
+        const Real F = ww * up;
+        div += is_lo ? F : -F;
+    }
+    return div;
+}
+
 }  // namespace rt
