@@ -267,47 +267,80 @@ __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real 
         const long long cc = (long long)blockIdx.x * kCellsPerBlock + cw;
         if (cc >= ncell) break;
         const Cell x = make_cell(G, cc);
+        Real lam[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + kWave * ch;
-            if (n >= N) continue;
+            const int m = n < N ? n : 0;
             // direct term: I*_c = I_c - (flux terms)
-            Real lam = G.mask[(size_t)x.gc * N + n] ? Real(0) : psi[x.c * N + n] * q[(size_t)x.gc * N + n];
+            lam[ch] = G.mask[(size_t)x.gc * N + m] ? Real(0) : psi[x.c * N + m] * q[(size_t)x.gc * N + m];
+        }
+        // axis by axis: the rows of the five cells and four faces the gather
+        // touches are resolved once per cell (uniform across the wavefront)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int coord = axis_coord(x, a);
-                const int len = axis_len(G, a);
-                const long long stride = axis_stride(G, a);
-                const int gstr = geo_stride(G, a);
-                const bool periodic = G.bc[a][0] == RT_BC_PERIODIC;
-                const Real *C = static_cast<const Real *>(G.C[a]);
-                Real v[5], ps[5], iv[5];
+        for (int a = 0; a < 3; ++a) {
+            const int coord = axis_coord(x, a);
+            const int len = axis_len(G, a);
+            const long long stride = axis_stride(G, a);
+            const int gstr = geo_stride(G, a);
+            const bool periodic = G.bc[a][0] == RT_BC_PERIODIC;
+            const Real *C = static_cast<const Real *>(G.C[a]);
+            AxisRows<Real> R;
+            axis_rows(G, Iin, x, a, R);
+            const Real *prow[5];
+            Real iv[5];
 #pragma unroll
-                for (int o = -2; o <= 2; ++o) {
-                    v[o + 2] = nbr(G, Iin, x, a, o, n);
-                    int idx = coord + o;
-                    bool inside = idx >= 0 && idx < len;
-                    if (!inside && periodic) {
-                        idx = ((idx % len) + len) % len;
-                        inside = true;
-                    }
-                    if (inside) {
-                        const long long c = x.c + (long long)(idx - coord) * stride;
-                        ps[o + 2] = psi[c * N + n];
-                        iv[o + 2] = invV[x.gc + (idx - coord) * gstr];
-                    } else {
-                        ps[o + 2] = Real(0);
-                        iv[o + 2] = Real(0);
-                    }
+            for (int o = -2; o <= 2; ++o) {
+                int idx = coord + o;
+                bool inside = idx >= 0 && idx < len;
+                if (!inside && periodic) {
+                    idx = ((idx % len) + len) % len;
+                    inside = true;
                 }
-                // faces at offsets fo = -1 .. 2 (face F between cells F-1 and F)
+                prow[o + 2] = inside ? psi + (x.c + (long long)(idx - coord) * stride) * N : nullptr;
+                iv[o + 2] = inside ? invV[x.gc + (idx - coord) * gstr] : Real(0);
+            }
+            // faces at offsets fo = -1 .. 2 (face F between cells F-1 and F)
+            const int8_t *Srow[4];
+            const Real *Crow[4];
+            bool fvalid[4], fon[4];
 #pragma unroll
-                for (int fo = -1; fo <= 2; ++fo) {
-                    const int Fraw = coord + fo;
-                    if (!periodic && (Fraw < 0 || Fraw > len)) continue;
-                    const int F = periodic ? ((Fraw % len) + len) % len : Fraw;
-                    const int fg = face_geo(G, a, F, x);
-                    const int s = G.sgn[a][(size_t)fg * N + n];
+            for (int f = 0; f < 4; ++f) {
+                const int fo = f - 1;
+                const int Fraw = coord + fo;
+                fvalid[f] = periodic || (Fraw >= 0 && Fraw <= len);
+                const int F = periodic ? ((Fraw % len) + len) % len : Fraw;
+                const int fg = face_geo(G, a, fvalid[f] ? F : 0, x);
+                Srow[f] = G.sgn[a] + (size_t)fg * N;
+                Crow[f] = C + (size_t)fg * N;
+                // luminosity face (on a periodic axis the face between the last
+                // and the first cell, where the forward step counts it)
+                fon[f] = a == G.lum_axis && fvalid[f] &&
+                         (periodic ? F == 0 : (G.lum_side == 1 ? F == len : F == 0));
+            }
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                if (n >= N) continue;
+                Real v[5], ps[5];
+                v[2] = Iin[x.c * N + n];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    Real val = R.nb[k][n];
+                    if (R.bs[k] != nullptr) {
+                        const int sb = R.bs[k][n];
+                        const bool out = k < 2 ? (sb < 0) : (sb > 0);
+                        val = out ? val : Real(0);
+                    }
+                    v[k < 2 ? k : k + 1] = val;
+                }
+#pragma unroll
+                for (int o = 0; o < 5; ++o) ps[o] = prow[o] ? prow[o][n] : Real(0);
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    if (!fvalid[f]) continue;
+                    const int fo = f - 1;
+                    const int s = Srow[f][n];
                     if (s == 0) continue;
                     const int u = s > 0 ? fo - 1 : fo;       // upwind cell, relative to x
                     if (u < -1 || u > 1) continue;
@@ -328,15 +361,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real 
                     }
                     // dJ/dF: the face is the upper face of cell fo-1 and the lower face of cell fo
                     Real lF = dtR * (ps[fo + 2] * iv[fo + 2] - ps[fo + 1] * iv[fo + 1]);
-                    // luminosity face (on a periodic axis the face between the last
-                    // and the first cell, where the forward step counts it)
-                    if (a == G.lum_axis) {
-                        const bool on = periodic ? F == 0 : (G.lum_side == 1 ? F == len : F == 0);
-                        if (on) lF += Real((G.lum_side == 1 ? -1.0 : 1.0) * lum_weight * dt * G.domega[n]);
-                    }
-                    lam += lF * C[(size_t)fg * N + n] * d;
+                    if (fon[f]) lF += Real((G.lum_side == 1 ? -1.0 : 1.0) * lum_weight * dt * G.domega[n]);
+                    lam[ch] += lF * Crow[f][n] * d;
                 }
             }
+        }
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int n = lane + kWave * ch;
+            if (n >= N) continue;
             if (G.has_edges) {
 #pragma unroll
                 for (int s = 0; s < kMaxNbr; ++s) {
@@ -349,10 +382,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real 
                     const int lo = G.edge_lo[e], hi = G.edge_hi[e];
                     const Real lF = -dtR * (psi[x.c * N + lo] / Real(G.domega[lo]) -
                                             psi[x.c * N + hi] / Real(G.domega[hi]));
-                    lam += lF * ww;
+                    lam[ch] += lF * ww;
                 }
             }
-            lamI0[x.c * N + n] = lam;
+            lamI0[x.c * N + n] = lam[ch];
         }
     }
 }
