@@ -37,6 +37,21 @@ Readings: masked bins carry zero intensity through the
 coupling and are left out of its angle sums; the fixed beam cells are
 re-imposed after the coupling; the luminosity is the energy flux the scheme
 itself moves through the chosen boundary face.
+
+Optional parts of the scheme (Sec. 2, flux calculation; Sec. 3, diffusion):
+
+  optical-depth-aware flux: per face an optical depth
+  tau = C_tau alpha_E dt / u^0^ from the face averages of the two adjacent
+  cells' alpha_E = (kappa_a + kappa_s) rho and u^0^, f = -expm1(-tau^2),
+  g_L/R = -f (1 + 1/n0bar_L/R) from each cell's own fluid, g = (g_L + g_R)/2,
+  and the upwind value times (1 - g_up + g); ghost cells carry the fluid of
+  the cell they copy (outflow) or wrap to (periodic).
+
+  two-stage integrator (Heun): stage 1 is the forward-Euler step U1 = U0 +
+  dt L(U0) with the coupling over dt; stage 2 forms ((U0 + U1) + dt L(U1))/2
+  for the radiation and (T0 + T1)/2 for the gas and applies the coupling over
+  dt/2.  The source, the T^0_alpha bookkeeping and the luminosity then enter
+  as (S1/2 + S2) and dt (l(U0) + l(U1))/2.
 """
 from __future__ import annotations
 
@@ -169,12 +184,50 @@ def face_states(P: torch.Tensor, d: int, n: int, recon: int):
     return IL, IR
 
 
-def spatial_fluxes(I: torch.Tensor, S: Setup, a: int) -> torch.Tensor:
-    """Face fluxes dA n^a n_0 I_up along axis a: [.., n+1 along dim 2-a, .., N]."""
+def fluid_pad(x: torch.Tensor, S: Setup, a: int) -> torch.Tensor:
+    """A per-cell field padded by one ghost cell along axis a: wrapped copies
+    on periodic boundaries, the adjacent cell's value on outflow/vacuum ones."""
+    prob = S.prob
+    d = 2 - a
+    n = x.shape[d]
+    lo = _nar(x, d, n - 1, 1) if prob.bc[a][0] == BC_PERIODIC else _nar(x, d, 0, 1)
+    hi = _nar(x, d, 0, 1) if prob.bc[a][1] == BC_PERIODIC else _nar(x, d, n - 1, 1)
+    return torch.cat([lo, x, hi], dim=d)
+
+
+def tau_factors(S: Setup, a: int, fl, dt: float):
+    """Optical-depth-aware flux factors (Sec. 2, flux calculation) at the n+1
+    faces along axis a for upwind L and upwind R: (1 - g_L + g, 1 - g_R + g)."""
+    rho, u, ka, ks = fl
+    d = 2 - a
+    n = rho.shape[d]
+    aE = (ka + ks) * rho
+    u0 = torch.sqrt(1.0 + (u * u).sum(-1))
+    nbar = u0[..., None] - torch.einsum("...i,ni->...n", u, S.nhat)
+    aEp, u0p = fluid_pad(aE, S, a), fluid_pad(u0, S, a)
+    nbp = fluid_pad(nbar, S, a)
+    aEf = 0.5 * (_nar(aEp, d, 0, n + 1) + _nar(aEp, d, 1, n + 1))
+    u0f = 0.5 * (_nar(u0p, d, 0, n + 1) + _nar(u0p, d, 1, n + 1))
+    tau = S.prob.tau_coeff * aEf * dt / u0f
+    f = -torch.expm1(-tau * tau)
+    gL = -f[..., None] * (1.0 + 1.0 / _nar(nbp, d, 0, n + 1))
+    gR = -f[..., None] * (1.0 + 1.0 / _nar(nbp, d, 1, n + 1))
+    g = 0.5 * (gL + gR)
+    # 1 - g_up + g, written so that it is exactly 1 when g_L = g_R
+    return 1.0 + (g - gL), 1.0 + (g - gR)
+
+
+def spatial_fluxes(I: torch.Tensor, S: Setup, a: int, fl=None, dt: float = 0.0) -> torch.Tensor:
+    """Face fluxes dA n^a n_0 I_up along axis a: [.., n+1 along dim 2-a, .., N].
+    With tau_coeff > 0 (fluid ``fl`` and dt given) the upwind value carries
+    the optical-depth-aware factor."""
     d = 2 - a
     n = I.shape[d]
     P = ghost_pad(I, S, a)
     IL, IR = face_states(P, d, n, S.prob.recon)
+    if S.prob.tau_coeff > 0.0 and fl is not None:
+        fL, fR = tau_factors(S, a, fl, dt)
+        IL, IR = IL * fL, IR * fR
     na = S.face_na[a]
     Iup = torch.where(na > 0, IL, torch.where(na < 0, IR, torch.zeros_like(IL)))
     return S.face_C[a] * Iup
@@ -194,12 +247,15 @@ def angular_divergence(I: torch.Tensor, S: Setup) -> torch.Tensor:
     return div
 
 
-def transport(I: torch.Tensor, S: Setup, dt: float, stats: dict | None = None):
+def transport(I: torch.Tensor, S: Setup, dt: float, stats: dict | None = None, fl=None,
+              base=None):
     """Flux divergence and primitive recovery: returns (I*, luminosity rate).
 
     The luminosity rate is the energy per unit time leaving through the
     boundary face (lum_axis, lum_side): minus the sum over that face's fluxes
-    weighted by solid angle, with the sign of the outward normal."""
+    weighted by solid angle, with the sign of the outward normal.
+    ``base`` = I0 makes this the second stage of the two-stage integrator:
+    Q* = (q I0 + q I - dt div(I)) / 2 (``dt`` is then the full step)."""
     prob = S.prob
     Q = S.q * I
     dQ = torch.zeros_like(I)
@@ -207,7 +263,7 @@ def transport(I: torch.Tensor, S: Setup, dt: float, stats: dict | None = None):
     for a in range(3):
         d = 2 - a
         n = I.shape[d]
-        F = spatial_fluxes(I, S, a)
+        F = spatial_fluxes(I, S, a, fl, dt)
         dQ = dQ + (_nar(F, d, 1, n) - _nar(F, d, 0, n))
         if a == prob.lum_axis:
             f = n if prob.lum_side == 1 else 0
@@ -215,10 +271,14 @@ def transport(I: torch.Tensor, S: Setup, dt: float, stats: dict | None = None):
             Ff = _nar(F, d, f, 1)
             lum_rate = -sgn * torch.sum(Ff * S.domega)
     Qs = Q - dt * dQ / S.vol[..., None] - dt * angular_divergence(I, S) / S.domega
+    if base is not None:
+        Qs = 0.5 * (S.q * base + Qs)
     Is = Qs / S.q
     if stats is not None:
+        # the two-stage step keeps half of stage 1's update (S1/2 + S2)
+        wgt = 0.5 if (prob.integrator == 2 and base is None) else 1.0
         removed = -(S.vol[..., None] * S.domega * Qs * S.mask).sum()
-        stats["masked_energy"] = stats.get("masked_energy", 0.0) + float(removed) * 1.0
+        stats["masked_energy"] = stats.get("masked_energy", 0.0) + float(removed) * wgt
     Is = torch.where(S.mask, torch.zeros_like(Is), Is)
     return Is, lum_rate
 
@@ -261,18 +321,30 @@ def coupling(Is: torch.Tensor, T: torch.Tensor, S: Setup, rho, u, ka, ks, dt,
     return Ip, Tp, dT0
 
 
-def step(I, T, S: Setup, rho, u, ka, ks, dt, beam_angle_idx=None,
-         stats: dict | None = None):
-    """One full step.  Returns (I+, T+, dT0 increment, dt * luminosity rate)."""
-    Is, lum_rate = transport(I, S, dt, stats)
-    Ip, Tp, dT0 = coupling(Is, T, S, rho, u, ka, ks, dt, stats)
+def _impose_beam(Ip, S: Setup, beam_angle_idx):
     prob = S.prob
     if prob.beam_mask is not None and beam_angle_idx is not None:
         bm = torch.as_tensor(prob.beam_mask)
         sel = torch.zeros_like(Ip, dtype=torch.bool)
         sel[..., beam_angle_idx] = bm
         Ip = torch.where(sel, torch.full_like(Ip, prob.beam_I), Ip)
-    return Ip, Tp, dT0, dt * lum_rate
+    return Ip
+
+
+def step(I, T, S: Setup, rho, u, ka, ks, dt, beam_angle_idx=None,
+         stats: dict | None = None):
+    """One full step.  Returns (I+, T+, dT0 increment, dt * luminosity rate)."""
+    fl = (rho, u, ka, ks)
+    Is, lum_rate = transport(I, S, dt, stats, fl)
+    Ip, Tp, dT0 = coupling(Is, T, S, rho, u, ka, ks, dt, stats)
+    Ip = _impose_beam(Ip, S, beam_angle_idx)
+    if S.prob.integrator != 2:
+        return Ip, Tp, dT0, dt * lum_rate
+    # second stage of the two-stage integrator
+    Is2, lum_rate2 = transport(Ip, S, dt, stats, fl, base=I)
+    Ip2, Tp2, dT02 = coupling(Is2, 0.5 * (T + Tp), S, rho, u, ka, ks, 0.5 * dt, stats)
+    Ip2 = _impose_beam(Ip2, S, beam_angle_idx)
+    return Ip2, Tp2, 0.5 * dT0 + dT02, 0.5 * dt * (lum_rate + lum_rate2)
 
 
 def fluid_tensors(prob):

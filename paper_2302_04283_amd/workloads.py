@@ -190,6 +190,10 @@ class Problem:
     lum_side: int = 1
     cfl: float = 0.3
     nsteps: int = 10
+    # time integrator: 1 = one forward-Euler stage per step, 2 = two-stage
+    # (Heun) integrator; optical-depth-aware flux constant (0 = free streaming)
+    integrator: int = 1
+    tau_coeff: float = 0.0
     # optional fixed-intensity beam cells
     beam_mask: Optional[np.ndarray] = None   # [n2][n1][n0] bool
     beam_I: float = 0.0
