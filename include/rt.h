@@ -75,6 +75,22 @@ enum { RT_BC_PERIODIC = 0, RT_BC_OUTFLOW_VACUUM = 1 };
  * beam_mask (optional, [n2][n1][n0], nonzero = beam cell): after each
  * step the intensity of direction beam_angle in those cells is set to
  * beam_I (a fixed-intensity source).
+ *
+ * integrator: 1 = one forward-Euler transport stage plus the implicit
+ * coupling per step; 2 = the two-stage (Heun) integrator of the paper's
+ * multi-stage scheme (Sec. 2 task list; second order in time, Sec. 3
+ * diffusion): stage 1 is the one-stage step, stage 2 forms
+ * ((U0 + U1) + dt L(U1))/2 and the gas temperature (T0 + T1)/2 and applies the
+ * coupling over dt/2; the T^0_alpha bookkeeping, the masked-energy ledger and
+ * the luminosity then carry (stage 1)/2 + stage 2.  rt_init_grid allocates
+ * one extra state and one cell array for it.
+ * tau_coeff: constant of the optical-depth-aware flux (Sec. 2, flux
+ * calculation): per face tau = tau_coeff alpha_E dt / u^0^ from the averages
+ * of the two adjacent cells, f = -expm1(-tau^2), g_L/R = -f (1 + 1/n0bar_L/R)
+ * from each cell's own fluid, g = (g_L + g_R)/2, and the upwind value times
+ * 1 + (g - g_up).  0 = free streaming.
+ * With integrator 2 or tau_coeff > 0 the step runs the general kernel, and
+ * rt_step_adjoint / the I_star output are not available (RT_EINVAL).
  */
 typedef struct {
     int32_t n[3];
@@ -96,6 +112,8 @@ typedef struct {
     const uint8_t *beam_mask;
     double beam_I;
     int32_t beam_angle;
+    int32_t integrator;        /* 1 or 2 (0 is taken as 1) */
+    double tau_coeff;          /* >= 0; 0 = free streaming */
 } rt_grid_desc;
 
 /*

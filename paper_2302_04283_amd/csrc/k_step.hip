@@ -22,6 +22,17 @@ constexpr int kCellsPerBlock = 16;
 __device__ __forceinline__ double wave_sum(double x) { return group_sum<kWave>(x); }
 __device__ __forceinline__ int wave_sum_i(int x) { return group_sum_i<kWave>(x); }
 
+// One stage of the step: Q* = gI q I + gB q Ib - beta dt (flux terms); the
+// coupling starts from gT T + gTb Tb (T alone without Tb) and runs over
+// beta dt; the bookkeeping and the masked-energy ledger are weighted by wS.
+// The one-stage step is {nullptr, nullptr, 1, 0, 1, 1, 0, 1}.
+template <typename Real>
+struct Stage {
+    const Real *Ib;
+    const double *Tb;
+    double gI, gB, beta, gT, gTb, wS;
+};
+
 template <typename Real, int NCH>
 __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restrict__ Iin,
                                                  Real *__restrict__ Iout, double *__restrict__ T,
@@ -32,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                                                  double *__restrict__ dT0,
                                                  double *__restrict__ partials,
                                                  int *__restrict__ nr_partial,
-                                                 Real *__restrict__ Istar) {
+                                                 Real *__restrict__ Istar, Stage<Real> st) {
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     const long long ncell = (long long)G.n0 * G.n1 * G.n2;
@@ -40,7 +51,9 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
     const Real *q = static_cast<const Real *>(G.q);
     const Real *vw = static_cast<const Real *>(G.vw);
     const Real *invV = static_cast<const Real *>(G.invV);
-    const Real dtR = Real(dt);
+    const double dts = st.beta * dt;      // this stage's time step
+    const Real dtR = Real(dts);
+    const bool tau_on = G.tau_coeff > 0.0;
     double lum_acc = 0.0, me_acc = 0.0;
     int nr_acc = 0;
     // angular-edge records of every direction, staged once per workgroup
@@ -68,7 +81,15 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
         for (int a = 0; a < 3; ++a) {
             AxisRows<Real> R;
             axis_rows(G, Iin, x, a, R);
-            if (R.ghost) {
+            if (tau_on) {
+                // the optical depth uses the full step in every stage
+                axis_fluid(G, x, a, rho, uvec, kap_a, kap_s, dt, R);
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int n = lane + kWave * ch;
+                    if (n < N) dq[ch] += axis_div<true, Real, true>(G, R, own[n], n, lum_acc);
+                }
+            } else if (R.ghost) {
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
                     const int n = lane + kWave * ch;
@@ -95,9 +116,11 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                 const Real Ic = own[n];
                 const Real div = G.has_edges ? angular_div_rec(s_adj, own, vwrow, n) : Real(0);
                 const Real qn = qrow[n];
-                const Real Qs = qn * Ic - dtR * ivol * dq[ch] - dtR * div / Real(G.domega[n]);
+                Real Qs = qn * Ic;
+                if (st.Ib) Qs = Real(st.gI) * Qs + Real(st.gB) * (qn * st.Ib[x.c * N + n]);
+                Qs = Qs - dtR * ivol * dq[ch] - dtR * div / Real(G.domega[n]);
                 if (mrow[n]) {
-                    me_acc -= volD * G.domega[n] * (double)Qs;
+                    me_acc -= st.wS * volD * G.domega[n] * (double)Qs;
                     continue;
                 }
                 Is[ch] = Qs / qn;
@@ -118,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
         const double u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
         const double rh = rho[x.c];
         const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh;
-        const double tau = (aa + as) * dt;
+        const double tau = (aa + as) * dts;
         const double n0 = G.n0u[x.gc];
         const uint8_t *mrow = G.mask + (size_t)x.gc * N;
         double nbv[NCH], rrv[NCH];
@@ -140,8 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
             sf[2] = fma(dom, nb * rr, sf[2]);
         }
         group_sum_v<kWave, 3>(sf);
-        const double Em = sf[0], A1 = sf[1], A2 = sf[2] * (dt / kFourPi);
-        const double Tm = T[x.c];
+        const double Em = sf[0], A1 = sf[1], A2 = sf[2] * (dts / kFourPi);
+        const double Tm = st.Tb ? st.gT * T[x.c] + st.gTb * st.Tb[x.c] : T[x.c];
         const double B4 = A2 * aa * G.a_rad;
         const double B1 = rh * G.cv * (1.0 - A2 * as);
         const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
@@ -150,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
         const double Ep = Em - rh * G.cv * (Tp - Tm);
         const double Tp2 = Tp * Tp;
         const double S = aa * G.a_rad * Tp2 * Tp2 + as * Ep;
-        const double cS = S * (dt / kFourPi);
+        const double cS = S * (dts / kFourPi);
         double sm[4] = {0.0, 0.0, 0.0, 0.0};
         const bool beam_cell = G.beam != nullptr && G.beam[x.c];
 #pragma unroll
@@ -185,8 +208,8 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                 const double *E0 = G.E0 + 16 * x.gc;
 #pragma unroll
                 for (int al = 0; al < 4; ++al)
-                    dT0[4 * x.c + al] -= n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
-                                               E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
+                    dT0[4 * x.c + al] -= st.wS * n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
+                                                       E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
             }
         }
     }
@@ -302,7 +325,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(DevGrid G, const Real *__res
 template <typename Real>
 int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                   const double *rho, const double *u, const double *ka, const double *ks,
-                  double dt, double *dT0, double *lum, void *Istar) {
+                  double dt, double *dT0, double *lum, void *Istar, const Stage<Real> &st,
+                  double lum_dt) {
     const DevGrid &G = g->dg;
     const int nblk = step_blocks(g);
     const int nch = (G.nang + kWave - 1) / kWave;
@@ -312,7 +336,7 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
     case NC:                                                                                   \
         hipLaunchKernelGGL((k_step<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in, out, T, \
                            rho, u, ka, ks, dt, dT0, g->partials, g->noroot_partial,           \
-                           static_cast<Real *>(Istar));                                        \
+                           static_cast<Real *>(Istar), st);                                    \
         break;
     switch (nch) {
         RT_LAUNCH(1)
@@ -328,7 +352,26 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
     }
 #undef RT_LAUNCH
     if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
-    return launch_finalize(g, s, nblk, dt, lum);
+    return launch_finalize(g, s, nblk, lum_dt, lum);
+}
+
+// The two-stage (Heun) step: stage 1 into the grid's stage buffers, stage 2
+// from them (and from I_in, T) into I_out, T.
+template <typename Real>
+int launch_rk2_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                 const double *rho, const double *u, const double *ka, const double *ks,
+                 double dt, double *dT0, double *lum) {
+    const size_t ncell = (size_t)g->dg.n0 * g->dg.n1 * g->dg.n2;
+    if (hipMemcpyAsync(g->stage_T, T, ncell * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+        return RT_EDEVICE;
+    const Stage<Real> s1{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 0.5};
+    int rc = launch_step_t<Real>(g, s, Iin, g->stage_I, g->stage_T, rho, u, ka, ks, dt, dT0, lum,
+                                 nullptr, s1, 0.5 * dt);
+    if (rc != RT_OK) return rc;
+    const Stage<Real> s2{static_cast<const Real *>(Iin), g->stage_T, 0.5, 0.5, 0.5, 0.5, 0.5, 1.0};
+    return launch_step_t<Real>(g, s, g->stage_I, Iout, T, rho, u, ka, ks, dt, dT0, lum, nullptr,
+                               s2, 0.5 * dt);
 }
 
 }  // namespace
@@ -352,9 +395,16 @@ int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *
         if (rc != RT_OK) return rc;
         return launch_finalize(g, s, g->march.grid, dt, lum);
     }
+    if (g->integrator == 2) {
+        if (g->precision == RT_F32)
+            return launch_rk2_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+        return launch_rk2_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+    }
     if (g->precision == RT_F32)
-        return launch_step_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, Istar);
-    return launch_step_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, Istar);
+        return launch_step_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, Istar,
+                                    Stage<float>{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0}, dt);
+    return launch_step_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, Istar,
+                                 Stage<double>{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0}, dt);
 }
 
 int launch_moments(rt_grid *g, hipStream_t s, const void *I, const double *u, double *R,

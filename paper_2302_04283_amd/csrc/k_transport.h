@@ -148,7 +148,55 @@ struct AxisRows {
     const int8_t *Slo, *Shi;
     bool ghost;                   // some offset lands on an outflow/vacuum ghost
     bool lum_lo, lum_hi;          // lower/upper face is the luminosity face
+    // optical-depth-aware flux: f of the lower/upper face and the fluid
+    // (u^0^, u^a^) of the cells at offsets -1, 0, +1
+    double f_lo, f_hi, u0n[3], un[3][3];
 };
+
+// Fluid data of the optical-depth-aware flux along axis a (Sec. 2, flux
+// calculation): f = -expm1(-tau^2) of both faces of the cell, tau =
+// tau_coeff alpha_E dt / u^0^ from the two adjacent cells' averages; a ghost
+// neighbour carries the fluid of the cell it copies (outflow) or wraps to.
+template <typename Real>
+__device__ __forceinline__ void axis_fluid(const DevGrid &G, const Cell &x, int a,
+                                           const double *__restrict__ rho,
+                                           const double *__restrict__ uvec,
+                                           const double *__restrict__ kap_a,
+                                           const double *__restrict__ kap_s, double dt,
+                                           AxisRows<Real> &R) {
+    const int coord = axis_coord(x, a);
+    const int len = axis_len(G, a);
+    const long long stride = axis_stride(G, a);
+    double aE[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        int idx = coord + k - 1;
+        if (idx < 0 || idx >= len) {
+            const int side = idx < 0 ? 0 : 1;
+            idx = G.bc[a][side] == RT_BC_PERIODIC ? ((idx % len) + len) % len : coord;
+        }
+        const long long c = x.c + (long long)(idx - coord) * stride;
+        const double u1 = uvec[3 * c], u2 = uvec[3 * c + 1], u3 = uvec[3 * c + 2];
+        R.un[k][0] = u1;
+        R.un[k][1] = u2;
+        R.un[k][2] = u3;
+        R.u0n[k] = sqrt(1.0 + u1 * u1 + u2 * u2 + u3 * u3);
+        aE[k] = (kap_a[c] + kap_s[c]) * rho[c];
+    }
+    const double tlo = G.tau_coeff * (0.5 * (aE[0] + aE[1])) * dt / (0.5 * (R.u0n[0] + R.u0n[1]));
+    const double thi = G.tau_coeff * (0.5 * (aE[1] + aE[2])) * dt / (0.5 * (R.u0n[1] + R.u0n[2]));
+    R.f_lo = -expm1(-tlo * tlo);
+    R.f_hi = -expm1(-thi * thi);
+}
+
+// Flux factors (1 + (g - g_L), 1 + (g - g_R)) of a face with interpolating
+// factor f between cells with fluid-frame n^0bar nL and nR.
+__device__ __forceinline__ void tau_face(double f, double nL, double nR, double &facL, double &facR) {
+    const double gL = -f * (1.0 + 1.0 / nL), gR = -f * (1.0 + 1.0 / nR);
+    const double g = 0.5 * (gL + gR);
+    facL = 1.0 + (g - gL);
+    facR = 1.0 + (g - gR);
+}
 
 template <typename Real>
 __device__ __forceinline__ void axis_rows(const DevGrid &G, const Real *__restrict__ Iin,
@@ -190,7 +238,7 @@ __device__ __forceinline__ void axis_rows(const DevGrid &G, const Real *__restri
 // Contribution of one axis to the flux divergence of direction n (the same
 // arithmetic as transport_dir, so the same I* bit for bit).  GHOST: some
 // neighbour along this axis is an outflow/vacuum ghost.
-template <bool GHOST, typename Real>
+template <bool GHOST, typename Real, bool TAU = false>
 __device__ __forceinline__ Real axis_div(const DevGrid &G, const AxisRows<Real> &R, Real Ic, int n,
                                          double &lum_acc) {
     Real v[5];
@@ -222,8 +270,20 @@ __device__ __forceinline__ Real axis_div(const DevGrid &G, const AxisRows<Real> 
         dlp = van_leer(v[3] - v[2], v[4] - v[3]);
     }
     const int slo = R.Slo[n], shi = R.Shi[n];
-    const Real ulo = slo > 0 ? v[1] + Real(0.5) * dlm : (slo < 0 ? v[2] - Real(0.5) * dl0 : Real(0));
-    const Real uhi = shi > 0 ? v[2] + Real(0.5) * dl0 : (shi < 0 ? v[3] - Real(0.5) * dlp : Real(0));
+    Real ulo = slo > 0 ? v[1] + Real(0.5) * dlm : (slo < 0 ? v[2] - Real(0.5) * dl0 : Real(0));
+    Real uhi = shi > 0 ? v[2] + Real(0.5) * dl0 : (shi < 0 ? v[3] - Real(0.5) * dlp : Real(0));
+    if constexpr (TAU) {
+        double nb[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            nb[k] = R.u0n[k] - (R.un[k][0] * G.nhat[3 * n] + R.un[k][1] * G.nhat[3 * n + 1] +
+                                R.un[k][2] * G.nhat[3 * n + 2]);
+        double fL, fR;
+        tau_face(R.f_lo, nb[0], nb[1], fL, fR);
+        ulo *= Real(slo > 0 ? fL : fR);
+        tau_face(R.f_hi, nb[1], nb[2], fL, fR);
+        uhi *= Real(shi > 0 ? fL : fR);
+    }
     const Real Flo = R.Clo[n] * ulo;
     const Real Fhi = R.Chi[n] * uhi;
     if (R.lum_hi) lum_acc -= G.domega[n] * (double)Fhi;

@@ -109,6 +109,9 @@ int check_desc(const rt_grid_desc *d) {
         if (d->beam_angle < 0 || d->beam_angle >= 10 * d->nlev * d->nlev + 2)
             return fail(RT_EINVAL, "beam_angle out of range");
     }
+    if (d->integrator < 0 || d->integrator > 2) return fail(RT_EINVAL, "integrator must be 1 or 2");
+    if (!(d->tau_coeff >= 0.0) || !std::isfinite(d->tau_coeff))
+        return fail(RT_EINVAL, "tau_coeff must be finite and >= 0");
     return RT_OK;
 }
 
@@ -186,6 +189,8 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
         v.lum_side = d->lum_side;
         v.a_rad = d->a_rad;
         v.cv = d->kb_mu_mp / (d->gamma_gas - 1.0);
+        v.tau_coeff = d->tau_coeff;
+        g->integrator = d->integrator == 2 ? 2 : 1;
         v.nhat = up.put(g->ang.nhat.data(), g->ang.nhat.size());
         v.domega = up.put(g->ang.domega.data(), g->ang.domega.size());
         v.adj_e = up.put(g->ang.adj_e.data(), g->ang.adj_e.size());
@@ -226,7 +231,8 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
             const bool allow = !(env && env[0] == '0');
             const bool cfg = rt::march_config(d->precision, N, sw, nc);
             const size_t lds = cfg ? rt::march_lds_bytes(d->precision, N, sw * nc) : 0;
-            if (allow && cfg && G == 1 && !t.has_edges && d->n[0] % rt::kTX == 0 &&
+            if (allow && cfg && G == 1 && !t.has_edges && g->integrator == 1 &&
+                !(d->tau_coeff > 0.0) && d->n[0] % rt::kTX == 0 &&
                 d->n[1] % rt::kTY == 0 &&
                 lds <= 150 * 1024) {
                 std::vector<double> q(N), iq(N), cx(N), cy(N), cz(N);
@@ -280,6 +286,11 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
         g->noroot_partial = up.zeros<int>((size_t)g->max_blocks);
         g->ledger = up.zeros<double>(1);
         g->noroot = up.zeros<long long>(1);
+        if (g->integrator == 2) {
+            // stage-1 state of the two-stage integrator
+            g->stage_I = up.zeros<unsigned char>(ncell * (size_t)N * (d->precision == RT_F32 ? 4 : 8));
+            g->stage_T = up.zeros<double>(ncell);
+        }
         (void)hipSetDevice(cur);
         if (up.code != RT_OK) {
             release(g);
@@ -370,6 +381,8 @@ int rt_step(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
     if (I_in == I_out) return fail(RT_EINVAL, "I_out must not alias I_in");
     if (I_star && (I_star == I_in || I_star == I_out))
         return fail(RT_EINVAL, "I_star must not alias I_in or I_out");
+    if (I_star && (g->integrator == 2 || g->dg.tau_coeff > 0.0))
+        return fail(RT_EINVAL, "I_star needs the one-stage step without the optical-depth-aware flux");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RT_EINVAL, "dt must be positive and finite");
     int cur = 0;
     (void)hipGetDevice(&cur);
@@ -394,6 +407,8 @@ int rt_step_adjoint(rt_grid *g, void *stream, const void *I_n, const double *T_n
         return fail(RT_EINVAL, "work must not alias the state or the adjoint buffers");
     if (I_star && (I_star == work || I_star == lamI_n))
         return fail(RT_EINVAL, "I_star must not alias work or lamI_n");
+    if (g->integrator == 2 || g->dg.tau_coeff > 0.0)
+        return fail(RT_EINVAL, "the adjoint covers the one-stage step without the optical-depth-aware flux");
     if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(lum_weight))
         return fail(RT_EINVAL, "dt must be positive and finite");
     int cur = 0;

@@ -60,6 +60,7 @@ struct DevGrid {
     int recon;
     int lum_axis, lum_side;
     double a_rad, cv;
+    double tau_coeff;             // optical-depth-aware flux constant (0 = off)
     // angle tables
     const double *nhat;           // [nang][3]
     const double *domega;         // [nang]
@@ -114,6 +115,9 @@ struct rt_grid {
     double *ledger = nullptr;     // [1] masked energy
     long long *noroot = nullptr;  // [1]
     int max_blocks = 0;
+    int integrator = 1;           // 1 or 2 stages per step
+    void *stage_I = nullptr;      // two-stage integrator: stage-1 intensities
+    double *stage_T = nullptr;    //                       stage-1 temperature
 };
 
 // kernel launchers (k_step.hip)

@@ -48,6 +48,8 @@ class RtGridDesc(C.Structure):
         ("beam_mask", C.POINTER(C.c_uint8)),
         ("beam_I", C.c_double),
         ("beam_angle", C.c_int32),
+        ("integrator", C.c_int32),
+        ("tau_coeff", C.c_double),
     ]
 
 
@@ -150,6 +152,8 @@ class Grid:
         d.a_rad = float(prob.a_rad)
         d.gamma_gas = float(prob.gamma_gas)
         d.kb_mu_mp = float(prob.kb_mu_mp)
+        d.integrator = int(getattr(prob, "integrator", 1))
+        d.tau_coeff = float(getattr(prob, "tau_coeff", 0.0))
         d.vol = _ptr(arr(prob.vol))
         d.gcov_c = _ptr(arr(prob.gcov_c))
         d.dgcov_c = _ptr(arr(prob.dgcov_c))
