@@ -294,6 +294,13 @@ def main():
             shapes["%d directions" % p2.nang] = {"value": p2.ncell * p2.nang * 20 / w2,
                                                   "ms_per_step": 1e3 * w2 / 20}
         out["paper_shapes_fp32"] = shapes
+        # the production scheme's options: two-stage integrator and the
+        # optical-depth-aware flux (general kernel), same 128^3 x 162 grid
+        p3 = W.make_problem(CONFIG)
+        p3.integrator, p3.tau_coeff = 2, 5.0
+        w3, _, _ = time_path(p3, rt.RT_F32, 10, 2, dt, dev)
+        out["two_stage_tau_fp32"] = {"value": ncell * nang * 10 / w3, "ms_per_step": 1e3 * w3 / 10,
+                                     "integrator": 2, "tau_coeff": 5.0, "kernel": "general"}
         print("[bench] context done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
