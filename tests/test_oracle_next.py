@@ -11,6 +11,8 @@ R3  optical-depth-aware flux: with a spatially uniform velocity the factor
     bit whatever the opacities (Sec. 2, flux calculation);
 R4  the optical-depth-aware flux keeps the flux form: in a periodic box the
     transport moves no energy, sum_c dV q (I* - I) = 0 per direction.
+R5  the factor departs from 1 as tau^2 at small optical depth and saturates
+    (f = 1) at large optical depth.
 The size of the factor's effect under velocity gradients rests on a reading
 of the paper (g = (g_L + g_R)/2) and is parity unpinned.
 """
@@ -115,3 +117,26 @@ def test_r4_tau_flux_keeps_flux_form():
     moved = ((S.q * (Is - I)) * S.vol[..., None]).sum((0, 1, 2))
     scale = ((S.q * I).abs() * S.vol[..., None]).sum((0, 1, 2))
     assert float((moved / scale).abs().max()) <= 1e-14
+
+
+def test_r5_tau_flux_onset_is_quadratic_and_saturates():
+    """f = -expm1(-tau^2): the factor's departure from 1 grows as tau^2 for
+    small optical depth (so as C_tau^2 at fixed fields) and stops growing
+    once f reaches 1 (tau^2 beyond double precision's reach of exp)."""
+    p = W.make_problem("c2", scale=(8, 6, 6))
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    fl = O.fluid_tensors(p)
+    I = torch.as_tensor(p.initial_intensity())
+    Is0, _ = O.transport(I, S, dt, None, None)
+
+    def dev(c):
+        p.tau_coeff = c
+        return O.transport(I, S, dt, None, fl)[0] - Is0
+
+    d1, d2 = dev(1e-3), dev(2e-3)
+    assert float(d1.abs().max()) > 0.0
+    assert float((d2 - 4.0 * d1).abs().max()) <= 1e-4 * float(d2.abs().max())
+    big1, big2 = dev(1e5), dev(1e6)
+    assert torch.isfinite(big1).all() and torch.equal(big1, big2)
+    assert float(big1.abs().max()) > float(d2.abs().max())
