@@ -52,6 +52,9 @@ Optional parts of the scheme (Sec. 2, flux calculation; Sec. 3, diffusion):
   for the radiation and (T0 + T1)/2 for the gas and applies the coupling over
   dt/2.  The source, the T^0_alpha bookkeeping and the luminosity then enter
   as (S1/2 + S2) and dt (l(U0) + l(U1))/2.
+
+  radiation-dominated velocity substitute (Sec. 2.5): see
+  ``radiation_velocity``; the rest of the coupling is unchanged.
 """
 from __future__ import annotations
 
@@ -287,11 +290,58 @@ def transport(I: torch.Tensor, S: Setup, dt: float, stats: dict | None = None, f
 # coupling
 # ----------------------------------------------------------------------------
 
-def coupling(Is: torch.Tensor, T: torch.Tensor, S: Setup, rho, u, ka, ks, dt,
-             stats: dict | None = None):
-    """Implicit radiation-matter coupling (Sec. 2.5).  Returns (I+, T+, dT0)."""
+def radiation_velocity(Is: torch.Tensor, T: torch.Tensor, S: Setup, rho, u, ka, ks, dt):
+    """Velocity used by the coupling in radiation-dominated cells (Sec. 2.5).
+
+    With the gas velocity u: E- = sum I* n0bar^2 dOmega; a cell is radiation
+    dominated when E- > rho + u_gas.  There the tetrad-frame moments
+    R^00 = sum I* dOmega, R^0a = sum n^a I* dOmega give v_rad = R^0a / R^00
+    and u_rad; the force on the gas is
+      G^a = -(alpha_a a_rad T^4 + alpha_s E-) u^a - alpha_E u_b R^ab,
+      u_b R^ab = -sum n^a n0bar I* dOmega,
+    the momentum densities T_gas^0a = w u^0 u^a, T_rad^0a = w u_rad^0 u_rad^a
+    (w = rho + u_gas + p), and the fraction per axis
+      f^a = clamp(G^a dt / (u^0 (T_rad^0a - T_gas^0a)), 0, 1)
+    blends u^a -> (1 - f^a) u^a + f^a u_rad^a.  Other cells (and cells with
+    R^00 <= 0 or |v_rad| >= 1) keep u.  Masked bins are left out of the sums."""
     prob = S.prob
     cv = prob.kb_mu_mp / (prob.gamma_gas - 1.0)
+    u0 = torch.sqrt(1.0 + (u * u).sum(-1))
+    nbar = u0[..., None] - torch.einsum("...i,ni->...n", u, S.nhat)
+    dOm = S.domega * (~S.mask)
+    Em = (Is * nbar * nbar * dOm).sum(-1)
+    R00 = (Is * dOm).sum(-1)
+    R0a = torch.einsum("...n,na->...a", Is * dOm, S.nhat)
+    uR = -torch.einsum("...n,na->...a", Is * nbar * dOm, S.nhat)
+    ugas = rho * cv * T
+    pgas = rho * prob.kb_mu_mp * T
+    w = rho + ugas + pgas
+    aa, as_ = ka * rho, ks * rho
+    safe = R00 > 0.0
+    v = torch.where(safe[..., None], R0a / torch.where(safe, R00, torch.ones_like(R00))[..., None],
+                    torch.zeros_like(R0a))
+    v2 = (v * v).sum(-1)
+    ok = safe & (v2 < 1.0) & (Em > rho + ugas)
+    ur0 = 1.0 / torch.sqrt(torch.where(ok, 1.0 - v2, torch.ones_like(v2)))
+    ur = ur0[..., None] * v
+    G = (-(aa * prob.a_rad * T ** 4 + as_ * Em)[..., None] * u - (aa + as_)[..., None] * uR)
+    gap = (w * ur0)[..., None] * ur - (w * u0)[..., None] * u
+    den = u0[..., None] * gap
+    f = torch.where(den != 0.0, G * dt / torch.where(den != 0.0, den, torch.ones_like(den)),
+                    torch.zeros_like(den)).clamp(0.0, 1.0)
+    us = (1.0 - f) * u + f * ur
+    return torch.where(ok[..., None], us, u)
+
+
+def coupling(Is: torch.Tensor, T: torch.Tensor, S: Setup, rho, u, ka, ks, dt,
+             stats: dict | None = None):
+    """Implicit radiation-matter coupling (Sec. 2.5).  Returns (I+, T+, dT0).
+    With rad_velocity set, radiation-dominated cells couple at the velocity
+    of ``radiation_velocity`` instead of the gas velocity."""
+    prob = S.prob
+    cv = prob.kb_mu_mp / (prob.gamma_gas - 1.0)
+    if getattr(prob, "rad_velocity", 0):
+        u = radiation_velocity(Is, T, S, rho, u, ka, ks, dt)
     u0 = torch.sqrt(1.0 + (u * u).sum(-1))                        # [cells]
     nbar = u0[..., None] - torch.einsum("...i,ni->...n", u, S.nhat)  # [cells, N]
     n0 = S.n_up_c[..., 0]                                          # n^0

@@ -194,6 +194,8 @@ class Problem:
     # (Heun) integrator; optical-depth-aware flux constant (0 = free streaming)
     integrator: int = 1
     tau_coeff: float = 0.0
+    # radiation-dominated velocity substitute in the coupling (0 = off)
+    rad_velocity: int = 0
     # optional fixed-intensity beam cells
     beam_mask: Optional[np.ndarray] = None   # [n2][n1][n0] bool
     beam_I: float = 0.0
