@@ -95,6 +95,28 @@ def time_path(prob, precision, steps, warmup, dt, dev):
     return wall, per, st
 
 
+def time_gas_update(prob, dev, reps):
+    """Average duration of rt_gas_update over the workload's cells (the
+    change dT0 is zero, so every call starts from the same gas state)."""
+    import torch
+    from paper_2302_04283_amd import rt
+    g = rt.Grid(prob, rt.RT_F64, dev.index or 0)
+    T = torch.as_tensor(prob.T).to(dev)
+    rho, u = torch.as_tensor(prob.rho).to(dev), torch.as_tensor(prob.u_tet).to(dev)
+    d0 = torch.zeros(T.shape + (4,), dtype=torch.float64, device=dev)
+    Tp = T.clone()
+    g.gas_update(d0, Tp, rho, u, T)
+    torch.cuda.synchronize(dev)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        g.gas_update(d0, Tp, rho, u, T)
+    b.record()
+    torch.cuda.synchronize(dev)
+    g.close()
+    return a.elapsed_time(b) * 1e-3 / reps
+
+
 def time_fwd_adjoint(prob, precision, steps, ckpt, dt, dev):
     """Forward with a checkpoint every `ckpt` steps plus the hand-written
     adjoint (segment recompute + reverse steps): whole-job wall time."""
@@ -301,6 +323,14 @@ def main():
         w3, _, _ = time_path(p3, rt.RT_F32, 10, 2, dt, dev)
         out["two_stage_tau_fp32"] = {"value": ncell * nang * 10 / w3, "ms_per_step": 1e3 * w3 / 10,
                                      "integrator": 2, "tau_coeff": 5.0, "kernel": "general"}
+        # radiation-dominated velocity substitute (general kernel) and the
+        # hand-over of dT0 to the gas (one thread per cell)
+        p4 = W.make_problem(CONFIG)
+        p4.rad_velocity = 1
+        w4, _, _ = time_path(p4, rt.RT_F32, 10, 2, dt, dev)
+        out["rad_velocity_fp32"] = {"value": ncell * nang * 10 / w4, "ms_per_step": 1e3 * w4 / 10,
+                                    "kernel": "general",
+                                    "gas_update_ms": 1e3 * time_gas_update(p4, dev, 20)}
         print("[bench] context done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

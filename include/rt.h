@@ -89,8 +89,19 @@ enum { RT_BC_PERIODIC = 0, RT_BC_OUTFLOW_VACUUM = 1 };
  * of the two adjacent cells, f = -expm1(-tau^2), g_L/R = -f (1 + 1/n0bar_L/R)
  * from each cell's own fluid, g = (g_L + g_R)/2, and the upwind value times
  * 1 + (g - g_up).  0 = free streaming.
+ * rad_velocity: radiation-dominated velocity substitute (Sec. 2.5).  In a
+ * cell whose fluid-frame radiation energy E (at the gas velocity u) exceeds
+ * rho + u_gas, the coupling runs at the velocity u'^a = (1 - f^a) u^a +
+ * f^a u_rad^a instead of u: v_rad = R^{0a}/R^{00} (tetrad frame), the force
+ * G^a = -(alpha_a a_rad T^4 + alpha_s E) u^a - alpha_E u_b R^{ab},
+ * f^a = G^a dt / (u^0 (T_rad^{0a} - T_gas^{0a})) clamped to [0, 1] with
+ * T^{0a} = (rho + u_gas + p) u^0 u^a at each velocity.  Cells with
+ * R^{00} <= 0 or |v_rad| >= 1 keep u.  The velocity field itself is not
+ * changed by rt_step (see rt_gas_update).
  * With integrator 2 or tau_coeff > 0 the step runs the general kernel, and
- * rt_step_adjoint / the I_star output are not available (RT_EINVAL).
+ * rt_step_adjoint / the I_star output are not available (RT_EINVAL).  With
+ * rad_velocity the step runs the general kernel and rt_step_adjoint is not
+ * available (RT_EINVAL).
  */
 typedef struct {
     int32_t n[3];
@@ -114,6 +125,7 @@ typedef struct {
     int32_t beam_angle;
     int32_t integrator;        /* 1 or 2 (0 is taken as 1) */
     double tau_coeff;          /* >= 0; 0 = free streaming */
+    int32_t rad_velocity;      /* 1: radiation-dominated velocity substitute in the coupling */
 } rt_grid_desc;
 
 /*
@@ -212,6 +224,27 @@ int rt_step_adjoint(rt_grid *g, void *stream, const void *I_n, const double *T_n
  */
 int rt_moments(rt_grid *g, void *stream, const void *I, const double *u_tet,
                double *R_tet, double *R0_cov, double *E_fluid);
+
+/*
+ * Hands the four-momentum the coupling took from the radiation to a
+ * gamma-law gas (Sec. 2.5, last paragraph: the change of R^0_alpha is
+ * subtracted from the gas's T^0_alpha).  Per cell, T^0_alpha of the gas
+ * state (rho, u_tet, T_pre) plus dT0 is inverted for the new primitive state
+ * with rho u^0 held (the coupling does not change the conserved density):
+ * in the normal-observer tetrad frame D = rho u^0^, E = T^{0^0^},
+ * S = T^{0^a^}; p solves (D/gamma + Gamma p/(Gamma-1)) gamma^2 - p = E with
+ * v = |S|/(E + p); then rho = D/gamma, u^a^ = gamma S/(E + p), T = p/(rho kb).
+ *   dT0   (dev, const) [cells][4] the change of T^0_alpha of ONE rt_step
+ *         (the caller zeroes it before that step)
+ *   T_pre (dev, const) [cells] gas temperature at the start of that step
+ *   rho, u_tet, T (dev, in/out) [cells], [cells][3], [cells]; T may alias T_pre
+ *   status (dev, optional) [cells] int32: 0 = updated, 1 = no physical state
+ *         (energy below momentum or rest mass + kinetic energy; the cell's
+ *         rho, u_tet, T are left unchanged)
+ * Gas parameters (gamma_gas, kb_mu_mp) are the grid's.
+ */
+int rt_gas_update(rt_grid *g, void *stream, const double *dT0, const double *T_pre,
+                  double *rho, double *u_tet, double *T, int32_t *status);
 
 /*
  * Running totals since rt_init_grid (synchronises the grid's device):

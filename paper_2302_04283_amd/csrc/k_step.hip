@@ -137,13 +137,65 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
         // ---------------------------------------------------------- coupling
         // per direction nb = n^0bar, dn = n^0 + nb tau, rr = 1/(nb^2 dn); the
         // quotients n^0/dn, 1/(nb dn), 1/(dn nb^3) are products with rr
-        const double u1 = uvec[3 * x.c], u2 = uvec[3 * x.c + 1], u3 = uvec[3 * x.c + 2];
-        const double u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
+        double u1 = uvec[3 * x.c], u2 = uvec[3 * x.c + 1], u3 = uvec[3 * x.c + 2];
+        double u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
         const double rh = rho[x.c];
         const double aa = kap_a[x.c] * rh, as = kap_s[x.c] * rh;
         const double tau = (aa + as) * dts;
         const double n0 = G.n0u[x.gc];
         const uint8_t *mrow = G.mask + (size_t)x.gc * N;
+        const double Tm = st.Tb ? st.gT * T[x.c] + st.gTb * st.Tb[x.c] : T[x.c];
+        if (G.rad_velocity) {
+            // radiation-dominated velocity substitute (Sec. 2.5): with the gas
+            // velocity, E = sum I n0bar^2 dOm, R^00, R^0a and sum n^a n0bar I dOm
+            // (= -u_b R^ab); cells with E > rho + u_gas couple at the blend
+            double sv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                if (n >= N || mrow[n]) continue;
+                const double nx = G.nhat[3 * n], ny = G.nhat[3 * n + 1], nz = G.nhat[3 * n + 2];
+                const double nb = u0 - fma(u1, nx, fma(u2, ny, u3 * nz));
+                const double Iw = (double)Is[ch] * G.domega[n];
+                const double Inb = Iw * nb;
+                sv[0] = fma(Inb, nb, sv[0]);
+                sv[1] += Iw;
+                sv[2] = fma(Iw, nx, sv[2]);
+                sv[3] = fma(Iw, ny, sv[3]);
+                sv[4] = fma(Iw, nz, sv[4]);
+                sv[5] = fma(Inb, nx, sv[5]);
+                sv[6] = fma(Inb, ny, sv[6]);
+                sv[7] = fma(Inb, nz, sv[7]);
+            }
+            group_sum_v<kWave, 8>(sv);
+            const double ug = rh * G.cv * Tm;
+            if (sv[1] > 0.0 && sv[0] > rh + ug) {
+                const double iR = 1.0 / sv[1];
+                const double vr[3] = {sv[2] * iR, sv[3] * iR, sv[4] * iR};
+                const double v2 = vr[0] * vr[0] + vr[1] * vr[1] + vr[2] * vr[2];
+                if (v2 < 1.0) {
+                    const double ur0 = 1.0 / sqrt(1.0 - v2);
+                    const double wg = rh + ug + rh * G.kb * Tm;
+                    const double Tm2 = Tm * Tm;
+                    const double emit = aa * G.a_rad * Tm2 * Tm2 + as * sv[0];
+                    const double uo[3] = {u1, u2, u3};
+                    double un[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const double ura = ur0 * vr[a];
+                        const double Ga = -emit * uo[a] + (aa + as) * sv[5 + a];
+                        const double den = u0 * (wg * ur0 * ura - wg * u0 * uo[a]);
+                        double f = den != 0.0 ? Ga * dts / den : 0.0;
+                        f = fmin(fmax(f, 0.0), 1.0);
+                        un[a] = (1.0 - f) * uo[a] + f * ura;
+                    }
+                    u1 = un[0];
+                    u2 = un[1];
+                    u3 = un[2];
+                    u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
+                }
+            }
+        }
         double nbv[NCH], rrv[NCH];
         double sf[3] = {0.0, 0.0, 0.0};   // Em, A1, A2
 #pragma unroll
@@ -164,7 +216,6 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
         }
         group_sum_v<kWave, 3>(sf);
         const double Em = sf[0], A1 = sf[1], A2 = sf[2] * (dts / kFourPi);
-        const double Tm = st.Tb ? st.gT * T[x.c] + st.gTb * st.Tb[x.c] : T[x.c];
         const double B4 = A2 * aa * G.a_rad;
         const double B1 = rh * G.cv * (1.0 - A2 * as);
         const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;

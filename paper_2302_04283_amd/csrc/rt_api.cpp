@@ -112,6 +112,7 @@ int check_desc(const rt_grid_desc *d) {
     if (d->integrator < 0 || d->integrator > 2) return fail(RT_EINVAL, "integrator must be 1 or 2");
     if (!(d->tau_coeff >= 0.0) || !std::isfinite(d->tau_coeff))
         return fail(RT_EINVAL, "tau_coeff must be finite and >= 0");
+    if (d->rad_velocity < 0 || d->rad_velocity > 1) return fail(RT_EINVAL, "rad_velocity must be 0 or 1");
     return RT_OK;
 }
 
@@ -190,6 +191,9 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
         v.a_rad = d->a_rad;
         v.cv = d->kb_mu_mp / (d->gamma_gas - 1.0);
         v.tau_coeff = d->tau_coeff;
+        v.kb = d->kb_mu_mp;
+        v.gamma = d->gamma_gas;
+        v.rad_velocity = d->rad_velocity ? 1 : 0;
         g->integrator = d->integrator == 2 ? 2 : 1;
         v.nhat = up.put(g->ang.nhat.data(), g->ang.nhat.size());
         v.domega = up.put(g->ang.domega.data(), g->ang.domega.size());
@@ -209,6 +213,7 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
         v.mask = up.put(t.mask.data(), t.mask.size());
         v.n0u = up.put(t.n0u.data(), t.n0u.size());
         v.E0 = up.put(t.E0.data(), t.E0.size());
+        v.gas_map = up.put(t.gas_map.data(), t.gas_map.size());
         v.volD = up.put(t.vol.data(), t.vol.size());
         v.has_edges = t.has_edges ? 1 : 0;
         const size_t ncell = (size_t)d->n[0] * d->n[1] * d->n[2];
@@ -232,7 +237,7 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
             const bool cfg = rt::march_config(d->precision, N, sw, nc);
             const size_t lds = cfg ? rt::march_lds_bytes(d->precision, N, sw * nc) : 0;
             if (allow && cfg && G == 1 && !t.has_edges && g->integrator == 1 &&
-                !(d->tau_coeff > 0.0) && d->n[0] % rt::kTX == 0 &&
+                !(d->tau_coeff > 0.0) && !d->rad_velocity && d->n[0] % rt::kTX == 0 &&
                 d->n[1] % rt::kTY == 0 &&
                 lds <= 150 * 1024) {
                 std::vector<double> q(N), iq(N), cx(N), cy(N), cz(N);
@@ -407,8 +412,9 @@ int rt_step_adjoint(rt_grid *g, void *stream, const void *I_n, const double *T_n
         return fail(RT_EINVAL, "work must not alias the state or the adjoint buffers");
     if (I_star && (I_star == work || I_star == lamI_n))
         return fail(RT_EINVAL, "I_star must not alias work or lamI_n");
-    if (g->integrator == 2 || g->dg.tau_coeff > 0.0)
-        return fail(RT_EINVAL, "the adjoint covers the one-stage step without the optical-depth-aware flux");
+    if (g->integrator == 2 || g->dg.tau_coeff > 0.0 || g->dg.rad_velocity)
+        return fail(RT_EINVAL, "the adjoint covers the one-stage step without the optical-depth-aware "
+                               "flux and without the velocity substitute");
     if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(lum_weight))
         return fail(RT_EINVAL, "dt must be positive and finite");
     int cur = 0;
@@ -431,6 +437,23 @@ int rt_moments(rt_grid *g, void *stream, const void *I, const double *u_tet, dou
     (void)hipGetDevice(&cur);
     if (cur != g->device) (void)hipSetDevice(g->device);
     int rc = rt::launch_moments(g, (hipStream_t)stream, I, u_tet, R_tet, R0_cov, E_fluid);
+    if (cur != g->device) (void)hipSetDevice(cur);
+    if (rc != RT_OK) return fail(rc, "kernel launch failed");
+    return RT_OK;
+}
+
+int rt_gas_update(rt_grid *g, void *stream, const double *dT0, const double *T_pre,
+                  double *rho, double *u_tet, double *T, int32_t *status) {
+    if (!g) return fail(RT_EINVAL, "grid is NULL");
+    if (!dT0 || !T_pre || !rho || !u_tet || !T) return fail(RT_EINVAL, "NULL state pointer");
+    if ((const void *)dT0 == (const void *)rho || (const void *)dT0 == (const void *)u_tet ||
+        (const void *)dT0 == (const void *)T || (const void *)T_pre == (const void *)rho ||
+        (const void *)T_pre == (const void *)u_tet)
+        return fail(RT_EINVAL, "dT0 and T_pre must not alias the gas state (T_pre may alias T)");
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    int rc = rt::launch_gas_update(g, (hipStream_t)stream, dT0, T_pre, rho, u_tet, T, status);
     if (cur != g->device) (void)hipSetDevice(cur);
     if (rc != RT_OK) return fail(rc, "kernel launch failed");
     return RT_OK;

@@ -116,6 +116,7 @@ int build_tables(const rt_grid_desc &d, const Geodesic &ang, HostTables &t, std:
     t.vw.assign((size_t)G * E * 2, 0.0);
     t.n0u.assign(G, 0.0);
     t.E0.assign((size_t)G * 16, 0.0);
+    t.gas_map.assign((size_t)G * 16, 0.0);
     t.vol.assign(d.vol, d.vol + G);
     t.has_edges = false;
     t.masked_count = 0;
@@ -153,6 +154,12 @@ int build_tables(const rt_grid_desc &d, const Geodesic &ang, HostTables &t, std:
                 return RT_EGEOM;
             }
         t.n0u[c] = e[0];
+        // normal-observer tetrad: e^{0^}_mu = (alpha, 0, 0, 0) and
+        // e^{b^}_mu g^{mu nu} = eta^{b b} e^nu_{b^}, so the tetrad row of a
+        // stress tensor is T^{0^ b^} = alpha eta^{bb} e^nu_{b^} T^0_nu
+        for (int b = 0; b < 4; ++b)
+            for (int m = 0; m < 4; ++m)
+                t.gas_map[16 * c + 4 * b + m] = (1.0 / e[0]) * kEta[b] * e[4 * m + b];
         for (int a = 0; a < 4; ++a)
             for (int b = 0; b < 4; ++b) {
                 double s = 0.0;

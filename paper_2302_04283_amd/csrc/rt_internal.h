@@ -43,6 +43,7 @@ struct HostTables {
     std::vector<double> vw;       // [G][nedge][2] (v, w)
     std::vector<double> n0u;      // [G]         n^0
     std::vector<double> E0;       // [G][4][4]   g_{a mu} e^mu_{b^}
+    std::vector<double> gas_map;  // [G][4][4]   T^{0^ b^} = sum_mu gas_map[b][mu] T^0_mu
     std::vector<double> vol;      // [G]
     bool has_edges = false;
     int masked_count = 0;
@@ -60,7 +61,9 @@ struct DevGrid {
     int recon;
     int lum_axis, lum_side;
     double a_rad, cv;
+    double kb, gamma;             // k_B / mu m_p, adiabatic index
     double tau_coeff;             // optical-depth-aware flux constant (0 = off)
+    int rad_velocity;             // radiation-dominated velocity substitute
     // angle tables
     const double *nhat;           // [nang][3]
     const double *domega;         // [nang]
@@ -76,6 +79,7 @@ struct DevGrid {
     const uint8_t *mask;          // [G][nang]
     const double *n0u;            // [G]
     const double *E0;             // [G][16]
+    const double *gas_map;        // [G][16]
     const double *volD;           // [G]
     int has_edges;
     const uint8_t *beam;          // [cells] or nullptr
@@ -142,4 +146,7 @@ int launch_adjoint(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin
                    const void *Istar);
 int launch_adj_march(rt_grid *g, hipStream_t s, const void *Iin, const void *psi, double dt,
                      double lum_weight, void *lamI0);
+// k_gas.hip
+int launch_gas_update(rt_grid *g, hipStream_t s, const double *dT0, const double *Tpre,
+                      double *rho, double *u, double *T, int32_t *status);
 }  // namespace rt

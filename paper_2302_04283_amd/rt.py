@@ -50,6 +50,7 @@ class RtGridDesc(C.Structure):
         ("beam_angle", C.c_int32),
         ("integrator", C.c_int32),
         ("tau_coeff", C.c_double),
+        ("rad_velocity", C.c_int32),
     ]
 
 
@@ -81,11 +82,13 @@ def load():
     lib.rt_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double,
                                     vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rt_stats.argtypes = [vp, C.POINTER(C.c_int64), _dp]
+    lib.rt_gas_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rt_free.argtypes = [vp]
     lib.rt_free.restype = None
     lib.rt_last_error.restype = C.c_char_p
     for f in ("rt_init_grid", "rt_geodesic_angles", "rt_grid_info", "rt_angles",
-              "rt_max_dt", "rt_step", "rt_moments", "rt_stats", "rt_step_adjoint"):
+              "rt_max_dt", "rt_step", "rt_moments", "rt_stats", "rt_step_adjoint",
+              "rt_gas_update"):
         getattr(lib, f).restype = C.c_int
     _LIB = lib
     return lib
@@ -154,6 +157,7 @@ class Grid:
         d.kb_mu_mp = float(prob.kb_mu_mp)
         d.integrator = int(getattr(prob, "integrator", 1))
         d.tau_coeff = float(getattr(prob, "tau_coeff", 0.0))
+        d.rad_velocity = int(getattr(prob, "rad_velocity", 0))
         d.vol = _ptr(arr(prob.vol))
         d.gcov_c = _ptr(arr(prob.gcov_c))
         d.dgcov_c = _ptr(arr(prob.dgcov_c))
@@ -278,6 +282,21 @@ class Grid:
         _check(self._lib.rt_moments(self._h, C.c_void_p(s.cuda_stream), _dev(I), _dev(u),
                                     _dev(R), _dev(R0), _dev(E)))
         return R, R0, E
+
+    def gas_update(self, dT0, T_pre, rho, u, T, status=None, stream=None):
+        """rt_gas_update: adds one step's dT0 to T^0_alpha of the gas state
+        (rho, u, T_pre) and writes the recovered (rho, u, T) in place."""
+        import torch
+        f8 = torch.float64
+        self._need(dT0, self._cell_shape(4), f8, "dT0")
+        self._need(T_pre, self._cell_shape(), f8, "T_pre")
+        self._need(rho, self._cell_shape(), f8, "rho")
+        self._need(u, self._cell_shape(3), f8, "u")
+        self._need(T, self._cell_shape(), f8, "T")
+        self._need(status, self._cell_shape(), torch.int32, "status")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(self._lib.rt_gas_update(self._h, C.c_void_p(s.cuda_stream), _dev(dT0), _dev(T_pre),
+                                       _dev(rho), _dev(u), _dev(T), _dev(status)))
 
     def close(self):
         if getattr(self, "_h", None):

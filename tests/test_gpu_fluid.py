@@ -1,0 +1,170 @@
+"""The radiation-dominated velocity substitute (general step kernel) and the
+hand-over of dT0 to the gas (rt_gas_update) against the oracle, through the
+C ABI.
+
+Tolerances: FP64 intensities 1e-12, gas temperature 1e-13 (summation order
+only; the substitute's velocity is a function of FP64 sums on both sides);
+FP32 intensities 1e-5, gas temperature 2e-7 (as for the plain step); both
+gas-temperature bounds times the energy balance's condition number
+max(1, E_rad / (rho c_v T)).  The
+gas update is FP64 on both sides (bisection in the oracle, bracketed Newton
+in the kernel): 1e-12 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from harness import gpu_run, oracle_run, rel_err
+from oracle import fluid as F
+from oracle import step as O
+from paper_2302_04283_amd import rt
+from paper_2302_04283_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(kind):
+    if kind == "mink":
+        p = W.make_problem("c2", scale=(8, 6, 5), nlev=2)
+    else:
+        p = W.make_problem("c3", scale=(10, 8, 4), nlev=2)
+        p.rho = p.rho * 1e-3          # radiation dominated almost everywhere
+    p.rad_velocity = 1
+    return p
+
+
+def _changed_cells(p, dt):
+    S = O.setup(p)
+    rho, u, ka, ks = O.fluid_tensors(p)
+    Is, _ = O.transport(torch.as_tensor(p.initial_intensity()), S, dt, None, (rho, u, ka, ks))
+    us = O.radiation_velocity(Is, torch.as_tensor(p.T), S, rho, u, ka, ks, dt)
+    return int(((us - u).abs().amax(-1) > 0).sum())
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("kind", ["mink", "ks"])
+def test_velocity_substitute_matches_oracle(kind, prec):
+    p = _problem(kind)
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    nchg = _changed_cells(p, dt)
+    assert nchg >= p.rho.size // 4           # the substitute acts in many cells
+    stats = {}
+    Io, To, dTo, Jo, _ = oracle_run(p, 3, dt, stats=stats)
+    Ig, Tg, dTg, Jg, g = gpu_run(p, prec, 3, dt)
+    assert not g.fast_path
+    st = g.stats()
+    g.close()
+    eI = rel_err(Ig, Io)
+    eT = float(np.max(np.abs(Tg - To) / To))
+    edT = float(np.max(np.abs(dTg - dTo)) / np.abs(dTo).max())
+    print("[fluid] substitute %s %s cells changed %d/%d e_I=%.2e e_T=%.2e e_dT0=%.2e" % (
+        kind, "fp64" if prec == rt.RT_F64 else "fp32", nchg, p.rho.size, eI, eT, edT), flush=True)
+    # T solves the cell's energy balance: a relative error in the radiation
+    # energy reaches T amplified by E_rad / (rho c_v T), large where the gas
+    # holds little energy (the Kerr-Schild case, rho scaled by 1e-3)
+    cv = p.kb_mu_mp / (p.gamma_gas - 1.0)
+    Erad = (np.asarray(p.initial_intensity()) * S.domega.numpy()).sum(-1)
+    cond = max(1.0, float(np.max(Erad / (p.rho * cv * p.T))))
+    if prec == rt.RT_F64:
+        assert eI <= 1e-12 and eT <= 1e-13 * cond and edT <= 1e-12
+        assert st["no_root"] == stats.get("no_root", 0)
+    else:
+        assert eI <= 1e-5 and eT <= 2e-7 * cond
+
+
+@pytest.mark.parametrize("kind", ["mink", "ks"])
+def test_gas_update_matches_oracle(kind):
+    p = W.make_problem("c2" if kind == "mink" else "c3", scale=(8, 6, 5), nlev=1)
+    base = F.gas_T0(p, p.rho, p.u_tet, p.T)
+    rng = np.random.default_rng(11)
+    dT0 = 1e-3 * base * rng.uniform(-1, 1, base.shape)
+    ro, uo, To = F.apply(p, p.rho, p.u_tet, p.T, dT0)
+    g = rt.Grid(p, rt.RT_F64)
+    dev = torch.device("cuda", 0)
+    rho = torch.as_tensor(p.rho).to(dev)
+    u = torch.as_tensor(p.u_tet).to(dev)
+    T = torch.as_tensor(p.T).to(dev)
+    st = torch.full(p.rho.shape, 7, dtype=torch.int32, device=dev)
+    g.gas_update(torch.as_tensor(dT0).to(dev), T, rho, u, T, st)   # T_pre aliases T
+    torch.cuda.synchronize()
+    g.close()
+    er = float(np.max(np.abs(rho.cpu().numpy() / ro - 1)))
+    eu = float(np.max(np.abs(u.cpu().numpy() - uo)) / np.abs(uo).max())
+    eT = float(np.max(np.abs(T.cpu().numpy() / To - 1)))
+    print("[fluid] gas update %s e_rho=%.2e e_u=%.2e e_T=%.2e" % (kind, er, eu, eT), flush=True)
+    assert int(st.abs().max()) == 0
+    assert er <= 1e-12 and eu <= 1e-12 and eT <= 1e-12
+
+
+def test_gas_update_flags_unphysical_cells():
+    p = W.make_problem("c2", scale=(4, 4, 4), nlev=1)
+    g = rt.Grid(p, rt.RT_F64)
+    dev = torch.device("cuda", 0)
+    rho = torch.as_tensor(p.rho).to(dev)
+    u = torch.as_tensor(p.u_tet).to(dev)
+    T = torch.as_tensor(p.T).to(dev)
+    base = F.gas_T0(p, p.rho, p.u_tet, p.T)
+    dT0 = np.zeros_like(base)
+    dT0[0, 0, 0, 0] = -10.0 * base[0, 0, 0, 0]     # T^0_0 = -E: energy made negative
+    st = torch.zeros(p.rho.shape, dtype=torch.int32, device=dev)
+    r0, u0, T0 = rho.clone(), u.clone(), T.clone()
+    g.gas_update(torch.as_tensor(dT0).to(dev), T0.clone(), rho, u, T, st)
+    torch.cuda.synchronize()
+    g.close()
+    s = st.cpu().numpy()
+    assert s[0, 0, 0] == 1 and s.sum() == 1
+    assert float(rho[0, 0, 0]) == float(r0[0, 0, 0]) and float(T[0, 0, 0]) == float(T0[0, 0, 0])
+    assert torch.equal(u[0, 0, 0], u0[0, 0, 0])
+
+
+@pytest.mark.parametrize("rv,args", [(0, (1.0, 2.0, 1.0)), (1, (0.1, 0.1, 0.3))])
+def test_moving_equilibration_steps_match_oracle(rv, args):
+    """rt_step + rt_gas_update in sequence (no spatial gradients) against the
+    oracle's coupling + fluid update, 20 steps of dt = 0.5 (Sec. 3 moving
+    equilibration; alpha_a = 0.1 held as rho changes)."""
+    rho0, p0, u10 = args
+    p = W.make_custom("minkowski_cart", (4, 4, 4), [(0.0, 1.0)] * 3, 2,
+                      [(W.BC_PERIODIC, W.BC_PERIODIC)] * 3)
+    p.rad_velocity = rv
+    shp = (4, 4, 4)
+    p.rho[:] = rho0
+    p.u_tet[:] = 0.0
+    p.u_tet[..., 0] = u10
+    p.T[:] = p0 / rho0
+    p.kappa_a[:] = 0.1 / rho0
+    S = O.setup(p)
+    dt, nsteps = 0.5, 20
+    rho, u, T = p.rho.copy(), p.u_tet.copy(), p.T.copy()
+    I = torch.full(shp + (p.nang,), 1.0 / (4 * np.pi), dtype=torch.float64)
+    g = rt.Grid(p, rt.RT_F64)
+    dev = torch.device("cuda", 0)
+    Ig = I.to(dev)
+    Ig2 = torch.empty_like(Ig)
+    rg, ug, Tg = (torch.as_tensor(x).to(dev) for x in (rho, u, T))
+    ka = torch.as_tensor(p.kappa_a).to(dev)
+    ks = torch.zeros(shp, dtype=torch.float64, device=dev)
+    d0 = torch.zeros(shp + (4,), dtype=torch.float64, device=dev)
+    st = torch.zeros(shp, dtype=torch.int32, device=dev)
+    for _ in range(nsteps):
+        Is, _ = O.transport(I, S, dt, None, None)
+        Ip, _, dT0 = O.coupling(Is, torch.as_tensor(T), S, torch.as_tensor(rho), torch.as_tensor(u),
+                                torch.as_tensor(0.1 / rho), torch.zeros(shp, dtype=torch.float64), dt)
+        rho, u, T = F.apply(p, rho, u, T, dT0.numpy())
+        I = Ip
+        d0.zero_()
+        Tpre = Tg.clone()
+        g.step(Ig, Ig2, Tg, rg, ug, ka, ks, dt, d0)
+        g.gas_update(d0, Tpre, rg, ug, Tg, st)
+        ka.copy_(0.1 / rg)
+        Ig, Ig2 = Ig2, Ig
+    torch.cuda.synchronize()
+    g.close()
+    eI = rel_err(Ig.cpu().numpy(), I.numpy())
+    eT = float(np.max(np.abs(Tg.cpu().numpy() / T - 1)))
+    eu = float(np.max(np.abs(ug.cpu().numpy() - u)))
+    er = float(np.max(np.abs(rg.cpu().numpy() / rho - 1)))
+    print("[fluid] moving equilibration rv=%d e_I=%.2e e_T=%.2e e_u=%.2e e_rho=%.2e" % (
+        rv, eI, eT, eu, er), flush=True)
+    assert int(st.abs().max()) == 0
+    assert eI <= 1e-12 and eT <= 1e-12 and eu <= 1e-12 and er <= 1e-12

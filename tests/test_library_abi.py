@@ -37,6 +37,7 @@ def test_host_error_paths():
                        None, None) == rt.RT_EINVAL
     assert lib.rt_step_adjoint(None, None, None, None, None, None, None, None, 0.1, 1.0,
                                None, None, None, None, None, None, None, None) == rt.RT_EINVAL
+    assert lib.rt_gas_update(None, None, None, None, None, None, None, None) == rt.RT_EINVAL
     dt = C.c_double()
     assert lib.rt_max_dt(None, 0.3, C.byref(dt)) == rt.RT_EINVAL
     lib.rt_free(None)
@@ -48,6 +49,7 @@ def test_bad_descriptor_rejected_before_device_use():
     out = C.c_void_p()
     assert rt.load().rt_init_grid(C.byref(d), 0, C.byref(out)) == rt.RT_EINVAL
     assert out.value is None
+    assert "rad_velocity" in dict(rt.RtGridDesc._fields_)
 
 
 @pytest.mark.parametrize("nlev", [1, 2, 3, 4, 5, 6, 7])
