@@ -148,6 +148,14 @@ __device__ __forceinline__ double half_slope(double a, double b, double c) {
 // increasing and convex on T >= 0, so the iterates decrease monotonically to
 // the root; stop when they no longer decrease.  No positive root (B0 >= 0 or
 // a non-finite coefficient): 1e-12 and bad = 1.
+// A root that over- or underflowed (coefficients near the ends of the double
+// range) counts as no usable root: the floor, like the other failures.
+__device__ __forceinline__ double root_or_floor(double T, int &bad) {
+    if (T > 0.0 && T < 1e300) return T;
+    bad = 1;
+    return 1e-12;
+}
+
 __device__ __forceinline__ double quartic_root(double B4, double B1, double B0, int &bad) {
     bad = 0;
     if (!(isfinite(B4) && isfinite(B1) && isfinite(B0)) || !(B0 < 0.0) || !(B1 > 0.0)) {
@@ -155,7 +163,7 @@ __device__ __forceinline__ double quartic_root(double B4, double B1, double B0, 
         return 1e-12;
     }
     const double lin = -B0 / B1;
-    if (!(B4 > 0.0)) return lin;
+    if (!(B4 > 0.0)) return root_or_floor(lin, bad);
     double T = fmin(lin, sqrt(sqrt(-B0 / B4)));
     for (int it = 0; it < 200; ++it) {
         const double T3 = T * T * T;
@@ -165,7 +173,7 @@ __device__ __forceinline__ double quartic_root(double B4, double B1, double B0, 
         if (!(Tn < T)) break;
         T = Tn;
     }
-    return T;
+    return root_or_floor(T, bad);
 }
 
 // Same root, fewer instructions: Newton steps use a refined reciprocal, and
@@ -183,7 +191,7 @@ __device__ __forceinline__ double quartic_root_fast(double B4, double B1, double
         return 1e-12;
     }
     const double lin = -B0 * rcp64(B1);
-    if (!(B4 > 0.0)) return -B0 / B1;
+    if (!(B4 > 0.0)) return root_or_floor(-B0 / B1, bad);
     const double x = -B0 * rcp64(B4);
     double T = lin;
     if (x < 1e30 && x > 1e-30) {
@@ -204,7 +212,7 @@ __device__ __forceinline__ double quartic_root_fast(double B4, double B1, double
         if (!(Tn < T)) break;
         T = Tn;
     }
-    return T;
+    return root_or_floor(T, bad);
 }
 
 }  // namespace rt

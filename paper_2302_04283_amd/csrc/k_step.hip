@@ -33,7 +33,10 @@ struct Stage {
     double gI, gB, beta, gT, gTb, wS;
 };
 
-template <typename Real, int NCH>
+// EXT = false compiles the plain one-stage step (no stage weights, no
+// optical-depth-aware flux, no velocity substitute) with the register budget
+// of the general-geometry case; EXT = true carries all three options.
+template <typename Real, int NCH, bool EXT>
 __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restrict__ Iin,
                                                  Real *__restrict__ Iout, double *__restrict__ T,
                                                  const double *__restrict__ rho,
@@ -51,9 +54,9 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
     const Real *q = static_cast<const Real *>(G.q);
     const Real *vw = static_cast<const Real *>(G.vw);
     const Real *invV = static_cast<const Real *>(G.invV);
-    const double dts = st.beta * dt;      // this stage's time step
+    const double dts = EXT ? st.beta * dt : dt;   // this stage's time step
     const Real dtR = Real(dts);
-    const bool tau_on = G.tau_coeff > 0.0;
+    const bool tau_on = EXT && G.tau_coeff > 0.0;
     double lum_acc = 0.0, me_acc = 0.0;
     int nr_acc = 0;
     // angular-edge records of every direction, staged once per workgroup
@@ -117,10 +120,10 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                 const Real div = G.has_edges ? angular_div_rec(s_adj, own, vwrow, n) : Real(0);
                 const Real qn = qrow[n];
                 Real Qs = qn * Ic;
-                if (st.Ib) Qs = Real(st.gI) * Qs + Real(st.gB) * (qn * st.Ib[x.c * N + n]);
+                if (EXT && st.Ib) Qs = Real(st.gI) * Qs + Real(st.gB) * (qn * st.Ib[x.c * N + n]);
                 Qs = Qs - dtR * ivol * dq[ch] - dtR * div / Real(G.domega[n]);
                 if (mrow[n]) {
-                    me_acc -= st.wS * volD * G.domega[n] * (double)Qs;
+                    me_acc -= (EXT ? st.wS : 1.0) * volD * G.domega[n] * (double)Qs;
                     continue;
                 }
                 Is[ch] = Qs / qn;
@@ -144,8 +147,8 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
         const double tau = (aa + as) * dts;
         const double n0 = G.n0u[x.gc];
         const uint8_t *mrow = G.mask + (size_t)x.gc * N;
-        const double Tm = st.Tb ? st.gT * T[x.c] + st.gTb * st.Tb[x.c] : T[x.c];
-        if (G.rad_velocity) {
+        const double Tm = (EXT && st.Tb) ? st.gT * T[x.c] + st.gTb * st.Tb[x.c] : T[x.c];
+        if (EXT && G.rad_velocity) {
             // radiation-dominated velocity substitute (Sec. 2.5): with the gas
             // velocity, E = sum I n0bar^2 dOm, R^00, R^0a and sum n^a n0bar I dOm
             // (= -u_b R^ab); cells with E > rho + u_gas couple at the blend
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                 const double *E0 = G.E0 + 16 * x.gc;
 #pragma unroll
                 for (int al = 0; al < 4; ++al)
-                    dT0[4 * x.c + al] -= st.wS * n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
+                    dT0[4 * x.c + al] -= (EXT ? st.wS : 1.0) * n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
                                                        E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
             }
         }
@@ -383,11 +386,17 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
     const int nch = (G.nang + kWave - 1) / kWave;
     const Real *in = static_cast<const Real *>(Iin);
     Real *out = static_cast<Real *>(Iout);
+    const bool ext = g->integrator == 2 || G.tau_coeff > 0.0 || G.rad_velocity;
 #define RT_LAUNCH(NC)                                                                          \
     case NC:                                                                                   \
-        hipLaunchKernelGGL((k_step<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in, out, T, \
-                           rho, u, ka, ks, dt, dT0, g->partials, g->noroot_partial,           \
-                           static_cast<Real *>(Istar), st);                                    \
+        if (ext)                                                                               \
+            hipLaunchKernelGGL((k_step<Real, NC, true>), dim3(nblk), dim3(kBlock), 0, s, G, in, \
+                               out, T, rho, u, ka, ks, dt, dT0, g->partials,                   \
+                               g->noroot_partial, static_cast<Real *>(Istar), st);             \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_step<Real, NC, false>), dim3(nblk), dim3(kBlock), 0, s, G,   \
+                               in, out, T, rho, u, ka, ks, dt, dT0, g->partials,               \
+                               g->noroot_partial, static_cast<Real *>(Istar), st);             \
         break;
     switch (nch) {
         RT_LAUNCH(1)
