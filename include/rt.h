@@ -98,6 +98,15 @@ enum { RT_BC_PERIODIC = 0, RT_BC_OUTFLOW_VACUUM = 1 };
  * T^{0a} = (rho + u_gas + p) u^0 u^a at each velocity.  Cells with
  * R^{00} <= 0 or |v_rad| >= 1 keep u.  The velocity field itself is not
  * changed by rt_step (see rt_gas_update).
+ * n_zeta, n_psi: with n_zeta > 0 the angular grid is the latitude-longitude
+ * grid of Sec. 2.6 (nlev is ignored): n_zeta + 1 circles of latitude equally
+ * spaced in cos(zeta) (zeta from the tetrad x^3 axis), n_psi + 1 meridians
+ * equally spaced in psi (from the x^1 axis), direction n = l n_psi + m at the
+ * middle of its cos(zeta) and psi ranges; n_zeta >= 2, n_psi even >= 2,
+ * n_zeta n_psi <= 512.
+ * ang_recon = 1 (latitude-longitude only): angular fluxes take van Leer PLM
+ * face values along the edge's coordinate line (Sec. 2.3), across a pole from
+ * the cell of the same row at psi + pi; rt_step_adjoint is then unavailable.
  * With integrator 2 or tau_coeff > 0 the step runs the general kernel, and
  * rt_step_adjoint / the I_star output are not available (RT_EINVAL).  With
  * rad_velocity the step runs the general kernel and rt_step_adjoint is not
@@ -126,6 +135,8 @@ typedef struct {
     int32_t integrator;        /* 1 or 2 (0 is taken as 1) */
     double tau_coeff;          /* >= 0; 0 = free streaming */
     int32_t rad_velocity;      /* 1: radiation-dominated velocity substitute in the coupling */
+    int32_t n_zeta, n_psi;     /* n_zeta > 0: latitude-longitude grid instead of the geodesic one */
+    int32_t ang_recon;         /* angular reconstruction: 0 = DC, 1 = PLM (latitude-longitude only) */
 } rt_grid_desc;
 
 /*
@@ -144,6 +155,13 @@ int rt_init_grid(const rt_grid_desc *desc, int device, rt_grid **out);
  * (e.g. a beam's) before building a grid.
  */
 int rt_geodesic_angles(int32_t nlev, double *nhat, double *domega);
+
+/*
+ * Host-only: the directions of the n_zeta x n_psi latitude-longitude grid in
+ * its order (n = l n_psi + m), nhat[nang][3] and domega[nang],
+ * nang = n_zeta n_psi.
+ */
+int rt_latlong_angles(int32_t n_zeta, int32_t n_psi, double *nhat, double *domega);
 
 /*
  * Number of directions and of angular-grid edges, and which step kernel the

@@ -42,6 +42,10 @@ class AngularGrid:
     length: np.ndarray   # [E] arc length
     mid: np.ndarray      # [E, 3] arc midpoint direction
     nu: np.ndarray       # [E, 3] unit normal at the midpoint, lo -> hi
+    # latitude-longitude grids only: the cells beyond lo and beyond hi along
+    # the edge's coordinate line (the PLM stencil ll, lo, hi, rr)
+    ll: np.ndarray = None
+    rr: np.ndarray = None
 
     @property
     def nang(self):
@@ -207,3 +211,72 @@ def build(nlev: int) -> AngularGrid:
         nu[e] = nrm
     return AngularGrid(nlev=nlev, nhat=nhat, domega=domega, polys=polys, lo=lo,
                        hi=hi, length=length, mid=mid, nu=nu)
+
+
+def build_latlong(n_zeta: int, n_psi: int) -> AngularGrid:
+    """Latitude-longitude grid (Sec. 2.6): n_zeta + 1 latitude lines equally
+    spaced in cos(zeta) from +1 to -1 (zeta from the +x^3 tetrad axis) and
+    n_psi + 1 longitudes equally spaced in psi from 0 to 2 pi (psi from +x^1
+    towards +x^2), so every cell has solid angle 4 pi / (n_zeta n_psi).
+    Cell n = l n_psi + m; its direction is at the middle of its cos(zeta) and
+    psi ranges.  Edges: constant-zeta arcs between rows l and l+1 (length
+    sin(zeta) dpsi, normal +zeta-hat) and meridian arcs between columns m and
+    m+1 (length dzeta, normal +psi-hat, midpoint at the middle of the arc).
+    The PLM stencil of an edge continues along its coordinate line; across a
+    pole it continues in the cell at psi + pi (Sec. 2.3), hence n_psi even."""
+    if n_zeta < 2 or n_psi < 2 or n_psi % 2:
+        raise ValueError("n_zeta >= 2 and an even n_psi >= 2 are required")
+    cz = 1.0 - 2.0 * np.arange(n_zeta + 1) / n_zeta
+    cz[-1] = -1.0
+    zb = np.arccos(cz)
+    dpsi = 2.0 * math.pi / n_psi
+    pb = dpsi * np.arange(n_psi + 1)
+    zc = np.arccos(0.5 * (cz[:-1] + cz[1:]))
+    pc = 0.5 * (pb[:-1] + pb[1:])
+
+    def sph(z, p):
+        return np.array([math.sin(z) * math.cos(p), math.sin(z) * math.sin(p), math.cos(z)])
+
+    def cell(l, m):
+        return l * n_psi + (m % n_psi)
+
+    N = n_zeta * n_psi
+    nhat = np.array([sph(zc[l], pc[m]) for l in range(n_zeta) for m in range(n_psi)])
+    domega = np.array([(cz[l] - cz[l + 1]) * dpsi for l in range(n_zeta) for _ in range(n_psi)])
+    polys = []
+    for l in range(n_zeta):
+        for m in range(n_psi):
+            P = [sph(zb[l], pb[m]), sph(zb[l + 1], pb[m]), sph(zb[l + 1], pb[m + 1]),
+                 sph(zb[l], pb[m + 1])]
+            if l == 0:
+                P = P[:3]                 # the north-pole corner is shared
+            elif l == n_zeta - 1:
+                P = [P[0], P[2], P[3]]    # the south-pole corner is shared
+            polys.append(np.array(P))
+    lo, hi, ll, rr, length, mid, nu = [], [], [], [], [], [], []
+    for l in range(n_zeta - 1):
+        z = zb[l + 1]
+        for m in range(n_psi):
+            lo.append(cell(l, m))
+            hi.append(cell(l + 1, m))
+            ll.append(cell(l - 1, m) if l > 0 else cell(0, m + n_psi // 2))
+            rr.append(cell(l + 2, m) if l + 2 < n_zeta else cell(n_zeta - 1, m + n_psi // 2))
+            length.append(math.sin(z) * dpsi)
+            mid.append(sph(z, pc[m]))
+            nu.append(np.array([math.cos(z) * math.cos(pc[m]), math.cos(z) * math.sin(pc[m]),
+                                -math.sin(z)]))
+    for l in range(n_zeta):
+        zm = 0.5 * (zb[l] + zb[l + 1])
+        for m in range(n_psi):
+            p = pb[m + 1]
+            lo.append(cell(l, m))
+            hi.append(cell(l, m + 1))
+            ll.append(cell(l, m - 1))
+            rr.append(cell(l, m + 2))
+            length.append(zb[l + 1] - zb[l])
+            mid.append(sph(zm, p))
+            nu.append(np.array([-math.sin(p), math.cos(p), 0.0]))
+    return AngularGrid(nlev=0, nhat=nhat, domega=domega, polys=polys,
+                       lo=np.array(lo, dtype=np.int64), hi=np.array(hi, dtype=np.int64),
+                       length=np.array(length), mid=np.array(mid), nu=np.array(nu),
+                       ll=np.array(ll, dtype=np.int64), rr=np.array(rr, dtype=np.int64))

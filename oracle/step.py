@@ -95,11 +95,16 @@ class Setup:
     edge_v: torch.Tensor      # [g2,g1,g0,E] L_e W.nu
     edge_w: torch.Tensor      # [g2,g1,g0,E] L_e W.nu n_0(m_e)
     omega: np.ndarray         # [g2,g1,g0,4,4,4]
+    edge_ll: torch.Tensor = None   # [E] PLM stencil beyond lo (latitude-longitude)
+    edge_rr: torch.Tensor = None   # [E] PLM stencil beyond hi
 
 
 def setup(prob) -> Setup:
     """Derived geometry of the scheme for a problem statement."""
-    ang = AG.build(prob.nlev)
+    ll = getattr(prob, "latlong", None)
+    ang = AG.build_latlong(*ll) if ll is not None else AG.build(prob.nlev)
+    if getattr(prob, "ang_recon", 0) and ang.ll is None:
+        raise ValueError("angular PLM needs the latitude-longitude grid")
     nhat = ang.nhat
     nu_c = GEO.n_up(prob.tet_c, nhat)
     nl_c = GEO.n_down(prob.gcov_c, prob.tet_c, nhat)
@@ -121,7 +126,9 @@ def setup(prob) -> Setup:
                  n_up_c=_t(nu_c), n_dn_c=_t(nl_c), q=_t(q), mask=torch.as_tensor(mask),
                  face_na=face_na, face_C=face_C, vol=_t(prob.vol),
                  edge_lo=torch.as_tensor(ang.lo), edge_hi=torch.as_tensor(ang.hi),
-                 edge_v=_t(v), edge_w=_t(w), omega=om)
+                 edge_v=_t(v), edge_w=_t(w), omega=om,
+                 edge_ll=None if ang.ll is None else torch.as_tensor(ang.ll),
+                 edge_rr=None if ang.rr is None else torch.as_tensor(ang.rr))
 
 
 def beam_angle(S: Setup) -> int:
@@ -236,12 +243,30 @@ def spatial_fluxes(I: torch.Tensor, S: Setup, a: int, fl=None, dt: float = 0.0) 
     return S.face_C[a] * Iup
 
 
+def _van_leer_slope(a, b, c):
+    """Harmonic-mean slope of b between neighbours a and c (index space)."""
+    dm, dp = b - a, c - b
+    prod = dm * dp
+    pos = prod > 0
+    den = torch.where(pos, dm + dp, torch.ones_like(dm))
+    return torch.where(pos, 2.0 * prod / den, torch.zeros_like(dm))
+
+
 def angular_divergence(I: torch.Tensor, S: Setup) -> torch.Tensor:
-    """sum over the edges of each angular cell of sigma F_e: [.., N]."""
+    """sum over the edges of each angular cell of sigma F_e: [.., N].
+    Upwind value: the cell value (DC) or, with angular PLM on the
+    latitude-longitude grid (Sec. 2.3), the van Leer face value from the
+    stencil (ll, lo, hi, rr) along the edge's coordinate line."""
     lo, hi = S.edge_lo, S.edge_hi
     v, w = S.edge_v, S.edge_w
     Ilo = I[..., lo]
     Ihi = I[..., hi]
+    if getattr(S.prob, "ang_recon", 0):
+        Ill = I[..., S.edge_ll]
+        Irr = I[..., S.edge_rr]
+        IL = Ilo + 0.5 * _van_leer_slope(Ill, Ilo, Ihi)
+        IR = Ihi - 0.5 * _van_leer_slope(Ilo, Ihi, Irr)
+        Ilo, Ihi = IL, IR
     Iup = torch.where(v > 0, Ilo, torch.where(v < 0, Ihi, torch.zeros_like(Ilo)))
     F = w * Iup
     div = torch.zeros_like(I)

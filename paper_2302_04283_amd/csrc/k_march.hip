@@ -504,13 +504,15 @@ int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T
 // Lane-group width and directions per lane for each supported direction count.
 bool march_config(int precision, int nang, int &sw, int &nc) {
     // instantiated (lane-group width, directions per lane) pairs
-    static const int f32[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 6}, {32, 8}};
-    static const int f64[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 6}};
+    static const int f32[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 4}, {32, 6}, {32, 8}};
+    static const int f64[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 4}, {32, 6}};
     int want = 0;
     if (const char *e = std::getenv("RT_MARCH_SW")) want = std::atoi(e);
     const int (*tab)[2] = precision == RT_F32 ? f32 : f64;
-    const int ntab = precision == RT_F32 ? 6 : 5;
-    // smallest group width whose directions-per-lane fits the register budget
+    const int ntab = precision == RT_F32 ? 7 : 6;
+    // smallest group width whose directions-per-lane fits the register
+    // budget; directions per lane must be exactly ceil(nang / width), since
+    // the kernel lets only the last chunk of a lane run past nang
     const int budget = 6;
     for (int w : {16, 32}) {
         if (want && w != want) continue;
@@ -557,6 +559,7 @@ int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double 
         RT_CASE(float, 16, 3)
         RT_CASE(float, 16, 6)
         RT_CASE(float, 32, 3)
+        RT_CASE(float, 32, 4)
         RT_CASE(float, 32, 6)
         RT_CASE(float, 32, 8)
     } else {
@@ -564,6 +567,7 @@ int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double 
         RT_CASE(double, 16, 3)
         RT_CASE(double, 16, 6)
         RT_CASE(double, 32, 3)
+        RT_CASE(double, 32, 4)
         RT_CASE(double, 32, 6)
     }
 #undef RT_CASE

@@ -117,7 +117,9 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                 Is[ch] = Real(0);
                 if (n >= N) continue;
                 const Real Ic = own[n];
-                const Real div = G.has_edges ? angular_div_rec(s_adj, own, vwrow, n) : Real(0);
+                const Real div = !G.has_edges ? Real(0)
+                                 : (G.ang_recon ? angular_div_plm(G, s_adj, own, vwrow, n)
+                                                : angular_div_rec(s_adj, own, vwrow, n));
                 const Real qn = qrow[n];
                 Real Qs = qn * Ic;
                 if (EXT && st.Ib) Qs = Real(st.gI) * Qs + Real(st.gB) * (qn * st.Ib[x.c * N + n]);

@@ -344,4 +344,32 @@ __device__ __forceinline__ Real angular_div_rec(const int *__restrict__ rec, con
     return div;
 }
 
+// angular_div with PLM face values (latitude-longitude grids, Sec. 2.3):
+// the lo side's value I_lo + delta/2 from (I_ll, I_lo, I_hi) and the hi
+// side's I_hi - delta/2 from (I_lo, I_hi, I_rr); both cells of an edge form
+// the same expression, so the fluxes telescope exactly.
+template <typename Real>
+__device__ __forceinline__ Real angular_div_plm(const DevGrid &G, const int *__restrict__ rec,
+                                                const Real *__restrict__ own,
+                                                const Real *__restrict__ vwrow, int n) {
+    Real div = Real(0);
+    const Real In = own[n];
+#pragma unroll
+    for (int s = 0; s < kMaxNbr; ++s) {
+        const int r = rec[n * kMaxNbr + s];
+        if (r < 0) break;
+        const int e = r & 0x7fff, m = (r >> 15) & 0x7fff;
+        const bool is_lo = (r >> 30) & 1;
+        const Real vv = vwrow[2 * e], ww = vwrow[2 * e + 1];
+        const Real Im = own[m];
+        const Real Ilo = is_lo ? In : Im, Ihi = is_lo ? Im : In;
+        const Real IL = Ilo + half_slope(own[G.edge_ll[e]], Ilo, Ihi);
+        const Real IR = Ihi - half_slope(Ilo, Ihi, own[G.edge_rr[e]]);
+        const Real up = vv > Real(0) ? IL : (vv < Real(0) ? IR : Real(0));
+        const Real F = ww * up;
+        div += is_lo ? F : -F;
+    }
+    return div;
+}
+
 }  // namespace rt

@@ -93,7 +93,17 @@ int check_desc(const rt_grid_desc *d) {
     }
     if ((long long)d->n[0] * d->n[1] * d->n[2] > (1LL << 31) - 1)
         return fail(RT_EINVAL, "too many cells");
-    if (d->nlev < 1 || d->nlev > 7) return fail(RT_EINVAL, "nlev must be in 1..7 (nang <= 492)");
+    const bool latlong = d->n_zeta > 0;
+    if (latlong) {
+        if (d->n_zeta < 2 || d->n_psi < 2 || (d->n_psi & 1) || d->n_zeta * d->n_psi > 512)
+            return fail(RT_EINVAL, "latitude-longitude grid needs n_zeta >= 2, an even n_psi >= 2 "
+                                   "and n_zeta n_psi <= 512");
+    } else if (d->nlev < 1 || d->nlev > 7) {
+        return fail(RT_EINVAL, "nlev must be in 1..7 (nang <= 492)");
+    }
+    if (d->ang_recon < 0 || d->ang_recon > 1 || (d->ang_recon == 1 && !latlong))
+        return fail(RT_EINVAL, "ang_recon must be 0, or 1 on a latitude-longitude grid");
+    const int nang = latlong ? d->n_zeta * d->n_psi : 10 * d->nlev * d->nlev + 2;
     if (d->precision != RT_F32 && d->precision != RT_F64) return fail(RT_EINVAL, "bad precision");
     if (d->recon != RT_RECON_DC && d->recon != RT_RECON_PLM) return fail(RT_EINVAL, "bad recon");
     if (d->lum_axis < 0 || d->lum_axis > 2 || d->lum_side < 0 || d->lum_side > 1)
@@ -106,7 +116,7 @@ int check_desc(const rt_grid_desc *d) {
     for (int c = 0; c < G; ++c)
         if (!(d->vol[c] > 0.0)) return fail(RT_EGEOM, "cell volumes must be positive");
     if (d->beam_mask) {
-        if (d->beam_angle < 0 || d->beam_angle >= 10 * d->nlev * d->nlev + 2)
+        if (d->beam_angle < 0 || d->beam_angle >= nang)
             return fail(RT_EINVAL, "beam_angle out of range");
     }
     if (d->integrator < 0 || d->integrator > 2) return fail(RT_EINVAL, "integrator must be 1 or 2");
@@ -135,7 +145,7 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
         g = new rt_grid();
         g->device = device;
         g->precision = d->precision;
-        g->ang = rt::build_geodesic(d->nlev);
+        g->ang = d->n_zeta > 0 ? rt::build_latlong(d->n_zeta, d->n_psi) : rt::build_geodesic(d->nlev);
         rt::HostTables t;
         std::string err;
         rc = rt::build_tables(*d, g->ang, t, err);
@@ -201,6 +211,9 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
         v.adj_s = up.put(g->ang.adj_s.data(), g->ang.adj_s.size());
         v.edge_lo = up.put(g->ang.lo.data(), g->ang.lo.size());
         v.edge_hi = up.put(g->ang.hi.data(), g->ang.hi.size());
+        v.ang_recon = d->ang_recon;
+        v.edge_ll = g->ang.ll.empty() ? nullptr : up.put(g->ang.ll.data(), g->ang.ll.size());
+        v.edge_rr = g->ang.rr.empty() ? nullptr : up.put(g->ang.rr.data(), g->ang.rr.size());
         v.q = up.real(t.q, d->precision);
         for (int a = 0; a < 3; ++a) {
             v.C[a] = up.real(t.C[a], d->precision);
@@ -332,6 +345,20 @@ int rt_geodesic_angles(int32_t nlev, double *nhat, double *domega) {
     return RT_OK;
 }
 
+int rt_latlong_angles(int32_t n_zeta, int32_t n_psi, double *nhat, double *domega) {
+    if (n_zeta < 2 || n_psi < 2 || (n_psi & 1) || n_zeta * n_psi > 512)
+        return fail(RT_EINVAL, "latitude-longitude grid needs n_zeta >= 2, an even n_psi >= 2 and "
+                               "n_zeta n_psi <= 512");
+    try {
+        rt::Geodesic a = rt::build_latlong(n_zeta, n_psi);
+        if (nhat) std::memcpy(nhat, a.nhat.data(), a.nhat.size() * sizeof(double));
+        if (domega) std::memcpy(domega, a.domega.data(), a.domega.size() * sizeof(double));
+    } catch (const std::exception &ex) {
+        return fail(RT_EINVAL, ex.what());
+    }
+    return RT_OK;
+}
+
 int rt_grid_info(const rt_grid *g, int32_t *nang, int32_t *nedge, int32_t *fast_path) {
     if (!g) return fail(RT_EINVAL, "grid is NULL");
     if (nang) *nang = g->ang.nang;
@@ -412,9 +439,9 @@ int rt_step_adjoint(rt_grid *g, void *stream, const void *I_n, const double *T_n
         return fail(RT_EINVAL, "work must not alias the state or the adjoint buffers");
     if (I_star && (I_star == work || I_star == lamI_n))
         return fail(RT_EINVAL, "I_star must not alias work or lamI_n");
-    if (g->integrator == 2 || g->dg.tau_coeff > 0.0 || g->dg.rad_velocity)
+    if (g->integrator == 2 || g->dg.tau_coeff > 0.0 || g->dg.rad_velocity || g->dg.ang_recon)
         return fail(RT_EINVAL, "the adjoint covers the one-stage step without the optical-depth-aware "
-                               "flux and without the velocity substitute");
+                               "flux, the velocity substitute and angular PLM");
     if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(lum_weight))
         return fail(RT_EINVAL, "dt must be positive and finite");
     int cur = 0;

@@ -28,9 +28,11 @@ struct Geodesic {
     std::vector<double> nu;       // [nedge][3]  lo -> hi
     std::vector<int> adj_e;       // [nang][6] edge index or -1
     std::vector<int> adj_s;       // [nang][6] +1 if the direction is the edge's lo, -1 if hi
+    std::vector<int> ll, rr;      // [nedge] PLM stencil beyond lo / hi (latitude-longitude only)
 };
 
 Geodesic build_geodesic(int nlev);
+Geodesic build_latlong(int n_zeta, int n_psi);
 
 // Derived host tables (FP64), geometry-cell major.
 struct HostTables {
@@ -70,6 +72,8 @@ struct DevGrid {
     const int *adj_e;             // [nang][6]
     const int *adj_s;             // [nang][6]
     const int *edge_lo, *edge_hi; // [nedge]
+    const int *edge_ll, *edge_rr; // [nedge] angular PLM stencil, or nullptr
+    int ang_recon;                // 0 = DC, 1 = PLM (latitude-longitude grids)
     // geometry tables in the intensity precision
     const void *q;                // [G][nang]
     const void *C[3];             // [F_a][nang]

@@ -51,6 +51,9 @@ class RtGridDesc(C.Structure):
         ("integrator", C.c_int32),
         ("tau_coeff", C.c_double),
         ("rad_velocity", C.c_int32),
+        ("n_zeta", C.c_int32),
+        ("n_psi", C.c_int32),
+        ("ang_recon", C.c_int32),
     ]
 
 
@@ -83,12 +86,13 @@ def load():
                                     vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rt_stats.argtypes = [vp, C.POINTER(C.c_int64), _dp]
     lib.rt_gas_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.rt_latlong_angles.argtypes = [C.c_int32, C.c_int32, _dp, _dp]
     lib.rt_free.argtypes = [vp]
     lib.rt_free.restype = None
     lib.rt_last_error.restype = C.c_char_p
     for f in ("rt_init_grid", "rt_geodesic_angles", "rt_grid_info", "rt_angles",
               "rt_max_dt", "rt_step", "rt_moments", "rt_stats", "rt_step_adjoint",
-              "rt_gas_update"):
+              "rt_gas_update", "rt_latlong_angles"):
         getattr(lib, f).restype = C.c_int
     _LIB = lib
     return lib
@@ -113,9 +117,18 @@ def geodesic_angles(nlev: int):
     return nh, do
 
 
-def beam_direction(nlev: int) -> int:
+def latlong_angles(n_zeta: int, n_psi: int):
+    """(nhat [nang,3], domega [nang]) of the library's latitude-longitude grid."""
+    lib = load()
+    nh = np.zeros((n_zeta * n_psi, 3))
+    do = np.zeros(n_zeta * n_psi)
+    _check(lib.rt_latlong_angles(int(n_zeta), int(n_psi), _ptr(nh), _ptr(do)))
+    return nh, do
+
+
+def beam_direction(nlev: int, latlong=None) -> int:
     """Direction with the largest x^1 component (the c2 beam)."""
-    nh, _ = geodesic_angles(nlev)
+    nh, _ = latlong_angles(*latlong) if latlong is not None else geodesic_angles(nlev)
     return int(np.argmax(nh[:, 0]))
 
 
@@ -158,6 +171,10 @@ class Grid:
         d.integrator = int(getattr(prob, "integrator", 1))
         d.tau_coeff = float(getattr(prob, "tau_coeff", 0.0))
         d.rad_velocity = int(getattr(prob, "rad_velocity", 0))
+        ll = getattr(prob, "latlong", None)
+        if ll is not None:
+            d.n_zeta, d.n_psi = int(ll[0]), int(ll[1])
+        d.ang_recon = int(getattr(prob, "ang_recon", 0))
         d.vol = _ptr(arr(prob.vol))
         d.gcov_c = _ptr(arr(prob.gcov_c))
         d.dgcov_c = _ptr(arr(prob.dgcov_c))
@@ -168,7 +185,7 @@ class Grid:
             bm = arr(prob.beam_mask, np.uint8)
             d.beam_mask = bm.ctypes.data_as(C.POINTER(C.c_uint8))
             d.beam_I = float(prob.beam_I)
-            self.beam_angle = beam_direction(prob.nlev)
+            self.beam_angle = beam_direction(prob.nlev, getattr(prob, "latlong", None))
             d.beam_angle = self.beam_angle
         h = C.c_void_p()
         _check(lib.rt_init_grid(C.byref(d), int(device), C.byref(h)))

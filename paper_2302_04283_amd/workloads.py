@@ -196,6 +196,11 @@ class Problem:
     tau_coeff: float = 0.0
     # radiation-dominated velocity substitute in the coupling (0 = off)
     rad_velocity: int = 0
+    # angular grid: None = geodesic of level nlev; (n_zeta, n_psi) = the
+    # latitude-longitude grid; angular reconstruction 0 = DC, 1 = PLM
+    # (latitude-longitude only)
+    latlong: Optional[tuple] = None
+    ang_recon: int = 0
     # optional fixed-intensity beam cells
     beam_mask: Optional[np.ndarray] = None   # [n2][n1][n0] bool
     beam_I: float = 0.0
@@ -211,6 +216,8 @@ class Problem:
 
     @property
     def nang(self) -> int:
+        if self.latlong is not None:
+            return int(self.latlong[0] * self.latlong[1])
         return 10 * self.nlev * self.nlev + 2
 
     def global_cell_index(self) -> np.ndarray:

@@ -60,3 +60,11 @@ def test_library_angle_table_matches_oracle(nlev):
     assert np.abs(nh - g.nhat).max() <= 1e-14
     assert np.abs(do - g.domega).max() <= 1e-14
     assert abs(do.sum() - 4 * math.pi) <= 1e-13
+
+
+@pytest.mark.parametrize("nz,npsi", [(2, 4), (8, 16), (16, 32)])
+def test_library_latlong_table_matches_oracle(nz, npsi):
+    nh, do = rt.latlong_angles(nz, npsi)
+    g = AG.build_latlong(nz, npsi)
+    assert np.abs(nh - g.nhat).max() <= 1e-14
+    assert np.abs(do - g.domega).max() <= 1e-14
