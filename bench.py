@@ -331,6 +331,19 @@ def main():
         out["rad_velocity_fp32"] = {"value": ncell * nang * 10 / w4, "ms_per_step": 1e3 * w4 / 10,
                                     "kernel": "general",
                                     "gas_update_ms": 1e3 * time_gas_update(p4, dev, 20)}
+        # the same box on the latitude-longitude grid, 8 x 16 directions (tiled)
+        p5 = W.make_problem(CONFIG)
+        p5.latlong = (8, 16)
+        w5, _, _ = time_path(p5, rt.RT_F32, 20, 2, dt, dev)
+        out["latlong_8x16_fp32"] = {"value": ncell * 128 * 20 / w5, "ms_per_step": 1e3 * w5 / 20}
+        # Kerr-Schild, 128 x 64 x 128 cells, 162 directions (general kernel)
+        p6 = W.make_problem("c3")
+        g6 = rt.Grid(p6, rt.RT_F32, dev.index or 0)
+        dt6 = g6.max_dt(p6.cfl)
+        g6.close()
+        w6, _, _ = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
+        out["kerr_schild_128x64x128_fp32"] = {"value": p6.ncell * p6.nang * 10 / w6,
+                                              "ms_per_step": 1e3 * w6 / 10, "kernel": "general"}
         print("[bench] context done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
