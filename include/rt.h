@@ -107,6 +107,11 @@ enum { RT_BC_PERIODIC = 0, RT_BC_OUTFLOW_VACUUM = 1 };
  * ang_recon = 1 (latitude-longitude only): angular fluxes take van Leer PLM
  * face values along the edge's coordinate line (Sec. 2.3), across a pole from
  * the cell of the same row at psi + pi; rt_step_adjoint is then unavailable.
+ * ang_recon = 2 (geodesic only): minimum-angle plane reconstruction (MAPR,
+ * Sec. 2.6): per direction, in the plane tangent at its centre, the candidate
+ * planes through the cell and each pair of consecutive neighbours; the one of
+ * smallest gradient gives the face value at each edge midpoint (first of equal
+ * minima in angular order); rt_step_adjoint is then unavailable.
  * With integrator 2 or tau_coeff > 0 the step runs the general kernel, and
  * rt_step_adjoint / the I_star output are not available (RT_EINVAL).  With
  * rad_velocity the step runs the general kernel and rt_step_adjoint is not
@@ -136,7 +141,8 @@ typedef struct {
     double tau_coeff;          /* >= 0; 0 = free streaming */
     int32_t rad_velocity;      /* 1: radiation-dominated velocity substitute in the coupling */
     int32_t n_zeta, n_psi;     /* n_zeta > 0: latitude-longitude grid instead of the geodesic one */
-    int32_t ang_recon;         /* angular reconstruction: 0 = DC, 1 = PLM (latitude-longitude only) */
+    int32_t ang_recon;         /* angular reconstruction: 0 = DC, 1 = PLM (latitude-longitude),
+                                  2 = MAPR (geodesic) */
 } rt_grid_desc;
 
 /*

@@ -280,3 +280,59 @@ def build_latlong(n_zeta: int, n_psi: int) -> AngularGrid:
                        lo=np.array(lo, dtype=np.int64), hi=np.array(hi, dtype=np.int64),
                        length=np.array(length), mid=np.array(mid), nu=np.array(nu),
                        ll=np.array(ll, dtype=np.int64), rr=np.array(rr, dtype=np.int64))
+
+
+def _tangent_basis(v):
+    ref = np.array([1.0, 0.0, 0.0]) if abs(v[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    t1 = _unit(ref - v * np.dot(ref, v))
+    return t1, np.cross(v, t1)
+
+
+def _gnomonic(p, v, t1, t2):
+    """Coordinates of unit vector p in the plane tangent to the sphere at v."""
+    s = np.dot(p, v)
+    return np.array([np.dot(p, t1) / s, np.dot(p, t2) / s])
+
+
+def mapr_geometry(g: AngularGrid):
+    """Geometry of minimum-angle plane reconstruction (MAPR) on a polygon grid
+    (Sec. 2.6; the method of Christov & Popov as used on hexagonal geodesic
+    grids by Florinski et al.).  In the plane tangent at each cell centre
+    (gnomonic coordinates) the neighbours are taken in angular order; every
+    pair of consecutive neighbours with the cell defines a candidate plane,
+    whose gradient solves the 2x2 system of the two neighbours' offsets.
+    The neighbours run counter-clockwise about the outward direction, starting
+    from the one of smallest index, so that the order (which breaks ties
+    between equally flat planes) does not depend on the tangent basis.
+    Returns (nbr [N, 6], pair_inv [N, 6, 2, 2], valid [N, 6], d_lo [E, 2],
+    d_hi [E, 2]): candidate i uses neighbours nbr[:, i] and nbr[:, i+1 mod k];
+    d_lo / d_hi are the edge midpoint's offsets from the lo / hi cell."""
+    N = g.nhat.shape[0]
+    nb = [[] for _ in range(N)]
+    for e in range(len(g.lo)):
+        nb[g.lo[e]].append(int(g.hi[e]))
+        nb[g.hi[e]].append(int(g.lo[e]))
+    nbr = np.zeros((N, 6), dtype=np.int64)
+    inv = np.zeros((N, 6, 2, 2))
+    valid = np.zeros((N, 6), dtype=bool)
+    basis = []
+    for c in range(N):
+        v = g.nhat[c]
+        t1, t2 = _tangent_basis(v)
+        basis.append((v, t1, t2))
+        xs = np.array([_gnomonic(g.nhat[k], v, t1, t2) for k in nb[c]])
+        order = list(np.argsort(np.arctan2(xs[:, 1], xs[:, 0])))
+        first = int(np.argmin([nb[c][i] for i in order]))
+        order = order[first:] + order[:first]
+        ks = [nb[c][i] for i in order]
+        xs = xs[order]
+        kk = len(ks)
+        nbr[c, :kk] = ks
+        nbr[c, kk:] = c
+        for i in range(kk):
+            A = np.array([xs[i], xs[(i + 1) % kk]])
+            inv[c, i] = np.linalg.inv(A)
+            valid[c, i] = True
+    d_lo = np.array([_gnomonic(g.mid[e], *basis[g.lo[e]]) for e in range(len(g.lo))])
+    d_hi = np.array([_gnomonic(g.mid[e], *basis[g.hi[e]]) for e in range(len(g.lo))])
+    return nbr, inv, valid, d_lo, d_hi

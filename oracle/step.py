@@ -69,6 +69,7 @@ from . import geometry as GEO
 from .quartic import quartic_root, quartic_root_count
 
 FOUR_PI = 4.0 * math.pi
+MAPR_TIE = 1e-10
 BC_PERIODIC = 0
 BC_OUTFLOW_VACUUM = 1
 
@@ -97,14 +98,26 @@ class Setup:
     omega: np.ndarray         # [g2,g1,g0,4,4,4]
     edge_ll: torch.Tensor = None   # [E] PLM stencil beyond lo (latitude-longitude)
     edge_rr: torch.Tensor = None   # [E] PLM stencil beyond hi
+    mapr: tuple = None             # MAPR geometry (geodesic grids)
 
 
 def setup(prob) -> Setup:
     """Derived geometry of the scheme for a problem statement."""
     ll = getattr(prob, "latlong", None)
     ang = AG.build_latlong(*ll) if ll is not None else AG.build(prob.nlev)
-    if getattr(prob, "ang_recon", 0) and ang.ll is None:
+    recon_a = getattr(prob, "ang_recon", 0)
+    if recon_a == 1 and ang.ll is None:
         raise ValueError("angular PLM needs the latitude-longitude grid")
+    if recon_a == 2 and ang.ll is not None:
+        raise ValueError("MAPR is the geodesic grid's reconstruction")
+    mapr = None
+    if recon_a == 2:
+        nbr, inv, valid, d_lo, d_hi = AG.mapr_geometry(ang)
+        cnt = valid.sum(1)
+        nxt = np.array([[(i + 1) % cnt[c] if i < cnt[c] else i for i in range(6)]
+                        for c in range(len(cnt))])
+        mapr = (torch.as_tensor(nbr), torch.as_tensor(nxt), _t(inv), torch.as_tensor(valid),
+                _t(d_lo), _t(d_hi))
     nhat = ang.nhat
     nu_c = GEO.n_up(prob.tet_c, nhat)
     nl_c = GEO.n_down(prob.gcov_c, prob.tet_c, nhat)
@@ -128,7 +141,7 @@ def setup(prob) -> Setup:
                  edge_lo=torch.as_tensor(ang.lo), edge_hi=torch.as_tensor(ang.hi),
                  edge_v=_t(v), edge_w=_t(w), omega=om,
                  edge_ll=None if ang.ll is None else torch.as_tensor(ang.ll),
-                 edge_rr=None if ang.rr is None else torch.as_tensor(ang.rr))
+                 edge_rr=None if ang.rr is None else torch.as_tensor(ang.rr), mapr=mapr)
 
 
 def beam_angle(S: Setup) -> int:
@@ -261,7 +274,24 @@ def angular_divergence(I: torch.Tensor, S: Setup) -> torch.Tensor:
     v, w = S.edge_v, S.edge_w
     Ilo = I[..., lo]
     Ihi = I[..., hi]
-    if getattr(S.prob, "ang_recon", 0):
+    if getattr(S.prob, "ang_recon", 0) == 2:
+        # MAPR: per cell-direction the flattest of the candidate planes
+        nbr, nxt, inv, valid, d_lo, d_hi = S.mapr
+        dI = I[..., nbr] - I[..., None]                          # [.., N, 6]
+        dJ = torch.gather(dI, -1, nxt.expand(dI.shape))
+        cand = torch.einsum("nikl,...nil->...nik", inv, torch.stack([dI, dJ], -1))
+        n2 = torch.where(valid, (cand * cand).sum(-1), torch.full_like(dI, math.inf))
+        # the first candidate (in the grid's order) within a relative
+        # tolerance of the flattest: ties between equally flat planes, which
+        # the grid's symmetry produces, are broken by position, not by
+        # rounding (tolerance: the precision of the path being checked)
+        tie = getattr(S.prob, "mapr_tie", MAPR_TIE)
+        near = n2 <= n2.min(-1, keepdim=True).values * (1.0 + tie)
+        k = torch.argmax(near.to(torch.int8), -1, keepdim=True)
+        grad = torch.gather(cand, -2, k[..., None].expand(k.shape + (2,))).squeeze(-2)
+        Ilo = Ilo + (grad[..., lo, :] * d_lo).sum(-1)
+        Ihi = Ihi + (grad[..., hi, :] * d_hi).sum(-1)
+    elif getattr(S.prob, "ang_recon", 0):
         Ill = I[..., S.edge_ll]
         Irr = I[..., S.edge_rr]
         IL = Ilo + 0.5 * _van_leer_slope(Ill, Ilo, Ihi)

@@ -19,6 +19,14 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kCellsPerBlock = 16;
+
+// LDS written by some lanes of a wavefront and read by others: order the
+// accesses within the wave (no workgroup barrier; waves run different cells)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __device__ __forceinline__ double wave_sum(double x) { return group_sum<kWave>(x); }
 __device__ __forceinline__ int wave_sum_i(int x) { return group_sum_i<kWave>(x); }
 
@@ -34,8 +42,9 @@ struct Stage {
 };
 
 // EXT = false compiles the plain one-stage step (no stage weights, no
-// optical-depth-aware flux, no velocity substitute) with the register budget
-// of the general-geometry case; EXT = true carries all three options.
+// optical-depth-aware flux, no velocity substitute, DC angular fluxes) with
+// the register budget of the general-geometry case; EXT = true carries all
+// of these options.
 template <typename Real, int NCH, bool EXT>
 __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restrict__ Iin,
                                                  Real *__restrict__ Iout, double *__restrict__ T,
@@ -61,6 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
     int nr_acc = 0;
     // angular-edge records of every direction, staged once per workgroup
     __shared__ int s_adj[kMaxAngGeneral * kMaxNbr];
+    // MAPR gradients, 2 N values per wave (dynamic; empty without MAPR)
+    extern __shared__ __align__(16) unsigned char s_dyn[];
     if (G.has_edges) {
         for (int i = threadIdx.x; i < N * kMaxNbr; i += kBlock) s_adj[i] = edge_record(G, i);
         __syncthreads();
@@ -106,6 +117,22 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                 }
             }
         }
+        Real *grad = reinterpret_cast<Real *>(s_dyn) + (size_t)wave * 2 * N;
+        const int arec = EXT ? G.ang_recon : 0;
+        if (arec == 2) {
+            // MAPR: every direction's gradient first, shared through LDS
+            wave_sync();
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                if (n >= N) continue;
+                Real gx, gy;
+                mapr_gradient(G, own, n, gx, gy);
+                grad[2 * n] = gx;
+                grad[2 * n + 1] = gy;
+            }
+            wave_sync();
+        }
         {
             const Real *qrow = q + (size_t)x.gc * N;
             const uint8_t *mrow = G.mask + (size_t)x.gc * N;
@@ -118,8 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
                 if (n >= N) continue;
                 const Real Ic = own[n];
                 const Real div = !G.has_edges ? Real(0)
-                                 : (G.ang_recon ? angular_div_plm(G, s_adj, own, vwrow, n)
-                                                : angular_div_rec(s_adj, own, vwrow, n));
+                                 : (arec == 2 ? angular_div_mapr(G, s_adj, own, vwrow, grad, n)
+                                    : arec == 1 ? angular_div_plm(G, s_adj, own, vwrow, n)
+                                                       : angular_div_rec(s_adj, own, vwrow, n));
                 const Real qn = qrow[n];
                 Real Qs = qn * Ic;
                 if (EXT && st.Ib) Qs = Real(st.gI) * Qs + Real(st.gB) * (qn * st.Ib[x.c * N + n]);
@@ -388,15 +416,16 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
     const int nch = (G.nang + kWave - 1) / kWave;
     const Real *in = static_cast<const Real *>(Iin);
     Real *out = static_cast<Real *>(Iout);
-    const bool ext = g->integrator == 2 || G.tau_coeff > 0.0 || G.rad_velocity;
+    const bool ext = g->integrator == 2 || G.tau_coeff > 0.0 || G.rad_velocity || G.ang_recon;
+    const size_t lds = G.ang_recon == 2 ? (size_t)kWavesPerBlock * 2 * G.nang * sizeof(Real) : 0;
 #define RT_LAUNCH(NC)                                                                          \
     case NC:                                                                                   \
         if (ext)                                                                               \
-            hipLaunchKernelGGL((k_step<Real, NC, true>), dim3(nblk), dim3(kBlock), 0, s, G, in, \
+            hipLaunchKernelGGL((k_step<Real, NC, true>), dim3(nblk), dim3(kBlock), lds, s, G, in, \
                                out, T, rho, u, ka, ks, dt, dT0, g->partials,                   \
                                g->noroot_partial, static_cast<Real *>(Istar), st);             \
         else                                                                                   \
-            hipLaunchKernelGGL((k_step<Real, NC, false>), dim3(nblk), dim3(kBlock), 0, s, G,   \
+            hipLaunchKernelGGL((k_step<Real, NC, false>), dim3(nblk), dim3(kBlock), lds, s, G, \
                                in, out, T, rho, u, ka, ks, dt, dT0, g->partials,               \
                                g->noroot_partial, static_cast<Real *>(Istar), st);             \
         break;

@@ -344,6 +344,72 @@ __device__ __forceinline__ Real angular_div_rec(const int *__restrict__ rec, con
     return div;
 }
 
+// MAPR gradient of direction n (geodesic grids, Sec. 2.6), in the tangent
+// coordinates of n: over the candidate planes through n and two consecutive
+// neighbours, the one of smallest |g|; among planes within a relative
+// tolerance of the smallest (ties that the grid's symmetry produces), the
+// first in the neighbour order.  The tolerance sits well above the rounding
+// of the intensity precision: 1e-10 in FP64, 1e-5 in FP32.
+template <typename Real>
+__device__ __forceinline__ Real mapr_tie() { return sizeof(Real) == 8 ? Real(1e-10) : Real(1e-5); }
+template <typename Real>
+__device__ __forceinline__ void mapr_gradient(const DevGrid &G, const Real *__restrict__ own, int n,
+                                              Real &gx, Real &gy) {
+    const int k = G.mapr_cnt[n];
+    const int *nb = G.mapr_nb + n * kMaxNbr;
+    const Real *M = static_cast<const Real *>(G.mapr_inv) + (size_t)n * kMaxNbr * 4;
+    const Real Ic = own[n];
+    Real d[kMaxNbr];
+#pragma unroll
+    for (int s = 0; s < kMaxNbr; ++s) d[s] = own[nb[s]] - Ic;
+    Real cx[kMaxNbr], cy[kMaxNbr], cq[kMaxNbr];
+    Real qmin = Real(0);
+#pragma unroll
+    for (int i = 0; i < kMaxNbr; ++i) {
+        const Real a = d[i], b = d[i + 1 < k ? i + 1 : 0];
+        cx[i] = M[4 * i] * a + M[4 * i + 1] * b;
+        cy[i] = M[4 * i + 2] * a + M[4 * i + 3] * b;
+        cq[i] = cx[i] * cx[i] + cy[i] * cy[i];
+        if (i < k && (i == 0 || cq[i] < qmin)) qmin = cq[i];
+    }
+    const Real lim = qmin * (Real(1) + mapr_tie<Real>());
+    gx = cx[0];
+    gy = cy[0];
+#pragma unroll
+    for (int i = kMaxNbr - 1; i >= 0; --i)
+        if (i < k && cq[i] <= lim) {
+            gx = cx[i];
+            gy = cy[i];
+        }
+}
+
+// angular_div with MAPR face values: I + g . d at the edge midpoint, g of
+// the cell the value is taken from (grad holds (gx, gy) per direction).
+template <typename Real>
+__device__ __forceinline__ Real angular_div_mapr(const DevGrid &G, const int *__restrict__ rec,
+                                                 const Real *__restrict__ own,
+                                                 const Real *__restrict__ vwrow,
+                                                 const Real *grad, int n) {
+    Real div = Real(0);
+    const Real *Dm = static_cast<const Real *>(G.mapr_d);
+#pragma unroll
+    for (int s = 0; s < kMaxNbr; ++s) {
+        const int r = rec[n * kMaxNbr + s];
+        if (r < 0) break;
+        const int e = r & 0x7fff, m = (r >> 15) & 0x7fff;
+        const bool is_lo = (r >> 30) & 1;
+        const int lo = is_lo ? n : m, hi = is_lo ? m : n;
+        const Real vv = vwrow[2 * e], ww = vwrow[2 * e + 1];
+        const Real *D = Dm + 4 * e;
+        const Real Ilo = own[lo] + grad[2 * lo] * D[0] + grad[2 * lo + 1] * D[1];
+        const Real Ihi = own[hi] + grad[2 * hi] * D[2] + grad[2 * hi + 1] * D[3];
+        const Real up = vv > Real(0) ? Ilo : (vv < Real(0) ? Ihi : Real(0));
+        const Real F = ww * up;
+        div += is_lo ? F : -F;
+    }
+    return div;
+}
+
 // angular_div with PLM face values (latitude-longitude grids, Sec. 2.3):
 // the lo side's value I_lo + delta/2 from (I_ll, I_lo, I_hi) and the hi
 // side's I_hi - delta/2 from (I_lo, I_hi, I_rr); both cells of an edge form

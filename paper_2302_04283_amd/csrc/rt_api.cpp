@@ -101,8 +101,10 @@ int check_desc(const rt_grid_desc *d) {
     } else if (d->nlev < 1 || d->nlev > 7) {
         return fail(RT_EINVAL, "nlev must be in 1..7 (nang <= 492)");
     }
-    if (d->ang_recon < 0 || d->ang_recon > 1 || (d->ang_recon == 1 && !latlong))
-        return fail(RT_EINVAL, "ang_recon must be 0, or 1 on a latitude-longitude grid");
+    if (d->ang_recon < 0 || d->ang_recon > 2 || (d->ang_recon == 1 && !latlong) ||
+        (d->ang_recon == 2 && latlong))
+        return fail(RT_EINVAL, "ang_recon must be 0, 1 (PLM, latitude-longitude grid) or 2 (MAPR, "
+                               "geodesic grid)");
     const int nang = latlong ? d->n_zeta * d->n_psi : 10 * d->nlev * d->nlev + 2;
     if (d->precision != RT_F32 && d->precision != RT_F64) return fail(RT_EINVAL, "bad precision");
     if (d->recon != RT_RECON_DC && d->recon != RT_RECON_PLM) return fail(RT_EINVAL, "bad recon");
@@ -214,6 +216,20 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
         v.ang_recon = d->ang_recon;
         v.edge_ll = g->ang.ll.empty() ? nullptr : up.put(g->ang.ll.data(), g->ang.ll.size());
         v.edge_rr = g->ang.rr.empty() ? nullptr : up.put(g->ang.rr.data(), g->ang.rr.size());
+        v.mapr_nb = nullptr;
+        v.mapr_cnt = nullptr;
+        v.mapr_inv = nullptr;
+        v.mapr_d = nullptr;
+        if (d->ang_recon == 2) {
+            std::vector<int> nb;
+            std::vector<double> inv, dd;
+            std::vector<int8_t> cnt;
+            rt::build_mapr(g->ang, nb, inv, cnt, dd);
+            v.mapr_nb = up.put(nb.data(), nb.size());
+            v.mapr_cnt = up.put(cnt.data(), cnt.size());
+            v.mapr_inv = up.real(inv, d->precision);
+            v.mapr_d = up.real(dd, d->precision);
+        }
         v.q = up.real(t.q, d->precision);
         for (int a = 0; a < 3; ++a) {
             v.C[a] = up.real(t.C[a], d->precision);

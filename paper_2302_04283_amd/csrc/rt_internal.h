@@ -33,6 +33,12 @@ struct Geodesic {
 
 Geodesic build_geodesic(int nlev);
 Geodesic build_latlong(int n_zeta, int n_psi);
+// MAPR tables (rt_mapr.cpp): per direction the neighbours in angular order
+// [nang][6] (padded with the direction itself), their count, the inverse
+// 2x2 matrices of the candidate planes [nang][6][4]; per edge the midpoint
+// offsets from lo and from hi [nedge][4]
+void build_mapr(const Geodesic &g, std::vector<int> &nb, std::vector<double> &inv,
+                std::vector<int8_t> &cnt, std::vector<double> &d);
 
 // Derived host tables (FP64), geometry-cell major.
 struct HostTables {
@@ -73,7 +79,11 @@ struct DevGrid {
     const int *adj_s;             // [nang][6]
     const int *edge_lo, *edge_hi; // [nedge]
     const int *edge_ll, *edge_rr; // [nedge] angular PLM stencil, or nullptr
-    int ang_recon;                // 0 = DC, 1 = PLM (latitude-longitude grids)
+    int ang_recon;                // 0 = DC, 1 = PLM (latitude-longitude), 2 = MAPR (geodesic)
+    const int *mapr_nb;           // [nang][6]
+    const int8_t *mapr_cnt;       // [nang]
+    const void *mapr_inv;         // [nang][6][4] intensity precision
+    const void *mapr_d;           // [nedge][4]   intensity precision
     // geometry tables in the intensity precision
     const void *q;                // [G][nang]
     const void *C[3];             // [F_a][nang]
