@@ -316,6 +316,12 @@ def main():
             shapes["%d directions" % p2.nang] = {"value": p2.ncell * p2.nang * 20 / w2,
                                                   "ms_per_step": 1e3 * w2 / 20}
         out["paper_shapes_fp32"] = shapes
+        # two-stage integrator alone (tiled kernel, two launches per step)
+        p2s = W.make_problem(CONFIG)
+        p2s.integrator = 2
+        w2s, _, _ = time_path(p2s, rt.RT_F32, 10, 2, dt, dev)
+        out["two_stage_fp32"] = {"value": ncell * nang * 10 / w2s, "ms_per_step": 1e3 * w2s / 10,
+                                 "integrator": 2, "kernel": "tiled"}
         # the production scheme's options: two-stage integrator and the
         # optical-depth-aware flux (general kernel), same 128^3 x 162 grid
         p3 = W.make_problem(CONFIG)
@@ -344,6 +350,11 @@ def main():
         w6, _, _ = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
         out["kerr_schild_128x64x128_fp32"] = {"value": p6.ncell * p6.nang * 10 / w6,
                                               "ms_per_step": 1e3 * w6 / 10, "kernel": "general"}
+        # the same with MAPR angular fluxes
+        p6.ang_recon = 2
+        w7, _, _ = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
+        out["kerr_schild_mapr_fp32"] = {"value": p6.ncell * p6.nang * 10 / w7,
+                                        "ms_per_step": 1e3 * w7 / 10, "kernel": "general"}
         print("[bench] context done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -34,14 +34,25 @@ namespace {
 #define RT_MARCH_WAVES_PER_EU 2
 #endif
 
-template <typename Real, int SW, int NC>
+// One stage of the two-stage integrator (STG = true): Q* = q (gI I + gB Ib)
+// - beta dt (flux terms), the coupling starts from gT T + gTb Tb and runs over
+// beta dt, and the bookkeeping and masked-energy ledger carry the weight wS.
+template <typename Real>
+struct MStage {
+    const Real *Ib;
+    const double *Tb;
+    double gI, gB, beta, gT, gTb, wS;
+};
+
+template <typename Real, int SW, int NC, bool STG = false>
 __global__ __launch_bounds__(kTC * SW) __attribute__((amdgpu_waves_per_eu(RT_MARCH_WAVES_PER_EU)))
 void k_march(
     DevGrid G, MarchInfo M, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
-    const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt,
+    const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt_step,
     double *__restrict__ dT0, double *__restrict__ partials, int *__restrict__ nr_partial,
-    Real *__restrict__ Istar) {
+    Real *__restrict__ Istar, MStage<Real> st) {
+    const double dt = STG ? st.beta * dt_step : dt_step;   // this stage's time step
     constexpr int NT = kTC * SW;
     constexpr int NW = NT / kWave;
     constexpr int NP = NC * SW;               // padded direction count
@@ -315,14 +326,20 @@ void k_march(
                 // signed coefficients: +-C/dV with the sign of the motion
                 const Real cx = s_tab[2 * NP + n], cy = s_tab[3 * NP + n], cz = s_tab[4 * NP + n];
                 const Real dq = fma(cz, Ibz - Iaz, fma(cy, Iby - Iay, cx * (Ibx - Iax)));
-                const Real Qs = fma(-dtR, dq, s_tab[n] * Ic);
+                Real Qb = Ic;
+                if constexpr (STG) {
+                    if (st.Ib)
+                        Qb = Real(st.gI) * Ic +
+                             Real(st.gB) * ((k < NC - 1 || n < N) ? st.Ib[cidx * N + n] : Real(0));
+                }
+                const Real Qs = fma(-dtR, dq, s_tab[n] * Qb);
                 if constexpr (sizeof(Real) == 4)
                     Is[k] = Qs * s_tab[NP + n];
                 else
                     Is[k] = Qs / s_tab[n];
                 if (doM) {
                     const bool msk = fm[k];
-                    me_acc -= msk ? vol * s_dom_all[n] * (double)Qs : 0.0;
+                    me_acc -= msk ? (STG ? st.wS : 1.0) * vol * s_dom_all[n] * (double)Qs : 0.0;
                     Is[k] = msk ? Real(0) : Is[k];
                 }
                 if (doS && (k < NC - 1 || n < N)) Istar[cidx * N + n] = Is[k];
@@ -357,7 +374,7 @@ void k_march(
         // ------------------------------------------------------ coupling
         const double u1 = s_fl[cl][0], u2 = s_fl[cl][1], u3 = s_fl[cl][2];
         const double rh = s_fl[cl][3], aa = s_fl[cl][4] * rh, as = s_fl[cl][5] * rh;
-        const double Tm = s_fl[cl][6];
+        const double Tm = (STG && st.Tb) ? st.gT * s_fl[cl][6] + st.gTb * st.Tb[cidx] : s_fl[cl][6];
         const double u0 = sqrt(1.0 + u1 * u1 + u2 * u2 + u3 * u3);
         const double tau = (aa + as) * dt;
         double Em = 0.0, A1 = 0.0, A2 = 0.0;
@@ -427,8 +444,9 @@ void k_march(
             if (a == 0) {
 #pragma unroll
                 for (int al = 0; al < 4; ++al)
-                    dT0[4 * cidx + al] -= n0u * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
-                                                 E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
+                    dT0[4 * cidx + al] -= (STG ? st.wS : 1.0) * n0u *
+                                          (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
+                                           E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
             }
         }
         // single buffer: every group must be done reading plane z first.
@@ -480,26 +498,60 @@ void k_march(
     }
 }
 
-template <typename Real, int SW, int NC>
+template <typename Real, int SW, int NC, bool STG = false>
 int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                const double *rho, const double *u, const double *ka, const double *ks,
-               double dt, double *dT0, Real *Istar) {
+               double dt, double *dT0, Real *Istar, const MStage<Real> &st = MStage<Real>{}) {
     const MarchInfo &M = g->march;
     static bool lds_set = false;   // one attribute call per instantiation
     if (!lds_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march<Real, SW, NC>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march<Real, SW, NC, STG>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)M.lds) != hipSuccess)
             return RT_EDEVICE;
         lds_set = true;
     }
-    hipLaunchKernelGGL((k_march<Real, SW, NC>), dim3(M.grid), dim3(kTC * SW), M.lds, s, g->dg, M,
-                       static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho, u, ka,
-                       ks, dt, dT0, g->partials, g->noroot_partial, Istar);
+    hipLaunchKernelGGL((k_march<Real, SW, NC, STG>), dim3(M.grid), dim3(kTC * SW), M.lds, s,
+                       g->dg, M, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho,
+                       u, ka, ks, dt, dT0, g->partials, g->noroot_partial, Istar, st);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
 }
 
+// The two-stage step on the tiled path (instantiated for 32 lanes x 6
+// directions): stage 1 into the grid's stage buffers, stage 2 from them and
+// from I_in, T into I_out, T; each stage's luminosity counts dt/2.
+template <typename Real>
+int march_rk2_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                const double *rho, const double *u, const double *ka, const double *ks,
+                double dt, double *dT0, double *lum) {
+    const size_t ncell = (size_t)g->dg.n0 * g->dg.n1 * g->dg.n2;
+    if (hipMemcpyAsync(g->stage_T, T, ncell * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+        return RT_EDEVICE;
+    const MStage<Real> s1{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 0.5};
+    int rc = launch_one<Real, 32, 6, true>(g, s, Iin, g->stage_I, g->stage_T, rho, u, ka, ks, dt,
+                                           dT0, nullptr, s1);
+    if (rc == RT_OK) rc = launch_finalize(g, s, g->march.grid, 0.5 * dt, lum);
+    if (rc != RT_OK) return rc;
+    const MStage<Real> s2{static_cast<const Real *>(Iin), g->stage_T, 0.5, 0.5, 0.5, 0.5, 0.5, 1.0};
+    rc = launch_one<Real, 32, 6, true>(g, s, g->stage_I, Iout, T, rho, u, ka, ks, dt, dT0, nullptr,
+                                       s2);
+    if (rc == RT_OK) rc = launch_finalize(g, s, g->march.grid, 0.5 * dt, lum);
+    return rc;
+}
+
 }  // namespace
+
+bool march_rk2_config(int sw, int nc) { return sw == 32 && nc == 6; }
+
+int launch_march_rk2(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                     const double *rho, const double *u, const double *ka, const double *ks,
+                     double dt, double *dT0, double *lum) {
+    if (!march_rk2_config(g->march.sw, g->march.nc)) return RT_EINVAL;
+    if (g->precision == RT_F32)
+        return march_rk2_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+    return march_rk2_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+}
 
 // Lane-group width and directions per lane for each supported direction count.
 bool march_config(int precision, int nang, int &sw, int &nc) {

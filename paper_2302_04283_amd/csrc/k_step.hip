@@ -42,10 +42,11 @@ struct Stage {
 };
 
 // EXT = false compiles the plain one-stage step (no stage weights, no
-// optical-depth-aware flux, no velocity substitute, DC angular fluxes) with
-// the register budget of the general-geometry case; EXT = true carries all
-// of these options.
-template <typename Real, int NCH, bool EXT>
+// optical-depth-aware flux, no velocity substitute) with the register budget
+// of the general-geometry case; EXT = true carries these options.
+// ANG: angular reconstruction 0 = DC, 1 = PLM, 2 = MAPR, compiled separately
+// so that each option pays only for its own registers.
+template <typename Real, int NCH, bool EXT, int ANG = 0>
 __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restrict__ Iin,
                                                  Real *__restrict__ Iout, double *__restrict__ T,
                                                  const double *__restrict__ rho,
@@ -118,8 +119,8 @@ __global__ __launch_bounds__(kBlock) void k_step(DevGrid G, const Real *__restri
             }
         }
         Real *grad = reinterpret_cast<Real *>(s_dyn) + (size_t)wave * 2 * N;
-        const int arec = EXT ? G.ang_recon : 0;
-        if (arec == 2) {
+        constexpr int arec = ANG;
+        if constexpr (arec == 2) {
             // MAPR: every direction's gradient first, shared through LDS
             wave_sync();
 #pragma unroll
@@ -416,18 +417,26 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
     const int nch = (G.nang + kWave - 1) / kWave;
     const Real *in = static_cast<const Real *>(Iin);
     Real *out = static_cast<Real *>(Iout);
-    const bool ext = g->integrator == 2 || G.tau_coeff > 0.0 || G.rad_velocity || G.ang_recon;
+    const bool ext = g->integrator == 2 || G.tau_coeff > 0.0 || G.rad_velocity;
     const size_t lds = G.ang_recon == 2 ? (size_t)kWavesPerBlock * 2 * G.nang * sizeof(Real) : 0;
+#define RT_LAUNCH_A(NC, E, A)                                                                  \
+    hipLaunchKernelGGL((k_step<Real, NC, E, A>), dim3(nblk), dim3(kBlock), lds, s, G, in, out,    \
+                       T, rho, u, ka, ks, dt, dT0, g->partials, g->noroot_partial,             \
+                       static_cast<Real *>(Istar), st)
+#define RT_LAUNCH_E(NC, E)                                                                     \
+    if (G.ang_recon == 2)                                                                      \
+        RT_LAUNCH_A(NC, E, 2);                                                                 \
+    else if (G.ang_recon == 1)                                                                 \
+        RT_LAUNCH_A(NC, E, 1);                                                                 \
+    else                                                                                       \
+        RT_LAUNCH_A(NC, E, 0);
 #define RT_LAUNCH(NC)                                                                          \
     case NC:                                                                                   \
-        if (ext)                                                                               \
-            hipLaunchKernelGGL((k_step<Real, NC, true>), dim3(nblk), dim3(kBlock), lds, s, G, in, \
-                               out, T, rho, u, ka, ks, dt, dT0, g->partials,                   \
-                               g->noroot_partial, static_cast<Real *>(Istar), st);             \
-        else                                                                                   \
-            hipLaunchKernelGGL((k_step<Real, NC, false>), dim3(nblk), dim3(kBlock), lds, s, G, \
-                               in, out, T, rho, u, ka, ks, dt, dT0, g->partials,               \
-                               g->noroot_partial, static_cast<Real *>(Istar), st);             \
+        if (ext) {                                                                             \
+            RT_LAUNCH_E(NC, true)                                                              \
+        } else {                                                                               \
+            RT_LAUNCH_E(NC, false)                                                             \
+        }                                                                                      \
         break;
     switch (nch) {
         RT_LAUNCH(1)
@@ -442,6 +451,8 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
             return RT_EINVAL;
     }
 #undef RT_LAUNCH
+#undef RT_LAUNCH_A
+#undef RT_LAUNCH_E
     if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
     return launch_finalize(g, s, nblk, lum_dt, lum);
 }
@@ -481,6 +492,8 @@ int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *l
 int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                 const double *rho, const double *u, const double *ka, const double *ks,
                 double dt, double *dT0, double *lum, void *Istar) {
+    if (g->march.enabled && g->integrator == 2)
+        return launch_march_rk2(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
     if (g->march.enabled) {
         int rc = launch_march(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar);
         if (rc != RT_OK) return rc;

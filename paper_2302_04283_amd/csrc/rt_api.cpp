@@ -265,7 +265,8 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
             const bool allow = !(env && env[0] == '0');
             const bool cfg = rt::march_config(d->precision, N, sw, nc);
             const size_t lds = cfg ? rt::march_lds_bytes(d->precision, N, sw * nc) : 0;
-            if (allow && cfg && G == 1 && !t.has_edges && g->integrator == 1 &&
+            if (allow && cfg && G == 1 && !t.has_edges &&
+                (g->integrator == 1 || rt::march_rk2_config(sw, nc)) &&
                 !(d->tau_coeff > 0.0) && !d->rad_velocity && d->n[0] % rt::kTX == 0 &&
                 d->n[1] % rt::kTY == 0 &&
                 lds <= 150 * 1024) {

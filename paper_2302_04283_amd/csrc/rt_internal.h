@@ -153,6 +153,10 @@ int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double 
                  const double *rho, const double *u, const double *ka, const double *ks,
                  double dt, double *dT0, void *Istar);
 int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *lum);
+bool march_rk2_config(int sw, int nc);
+int launch_march_rk2(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                     const double *rho, const double *u, const double *ka, const double *ks,
+                     double dt, double *dT0, double *lum);
 int launch_adjoint(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
                    const double *rho, const double *u, const double *ka, const double *ks,
                    double dt, double lum_weight, const void *lamI1, const double *lamT1,

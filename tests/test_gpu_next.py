@@ -74,3 +74,30 @@ def test_options_select_general_kernel_and_exclude_adjoint():
         g.step_adjoint(I, cell, cell, u, cell, cell, 0.01, I.clone(), cell.clone(), I.clone(),
                        cell.clone(), I.clone())
     g.close()
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+def test_two_stage_on_the_tiled_path_matches_oracle(prec):
+    """The two-stage integrator on the tiled kernel (162 directions, 32 lanes
+    x 6 directions per lane), with the collimated beam and the luminosity."""
+    p = W.make_problem("c2", scale=(8, 8, 8))
+    p.integrator = 2
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    stats = {}
+    Io, To, dTo, Jo, _ = oracle_run(p, 3, dt, stats=stats)
+    Ig, Tg, dTg, Jg, g = gpu_run(p, prec, 3, dt)
+    assert g.fast_path
+    st = g.stats()
+    g.close()
+    eI = rel_err(Ig, Io)
+    eT = float(np.max(np.abs(Tg - To) / To))
+    edT = float(np.max(np.abs(dTg - dTo)) / max(np.abs(dTo).max(), 1e-300))
+    eJ = abs(Jg - Jo) / max(abs(Jo), 1e-300)
+    print("[next] tiled integrator=2 %s e_I=%.2e e_T=%.2e e_dT0=%.2e e_J=%.2e" % (
+        "fp64" if prec == rt.RT_F64 else "fp32", eI, eT, edT, eJ), flush=True)
+    if prec == rt.RT_F64:
+        assert eI <= 1e-12 and eT <= 1e-13 and edT <= 1e-12 and eJ <= 1e-12
+        assert st["no_root"] == stats.get("no_root", 0)
+    else:
+        assert eI <= 1e-5 and eT <= 2e-7
