@@ -162,8 +162,9 @@ def _upload_initial(prob, dtype, dev):
     return out
 
 
-def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag):
+def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag, integrator=1):
     full = W.make_problem(cfg)
+    full.integrator = integrator
     dt = O.max_dt(O.setup(full), full.cfl)
     dev = torch.device("cuda", 0)
     g = rt.Grid(full, precision)
@@ -176,8 +177,9 @@ def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag):
         g.step(Ia, Ib, T, *args, dt)
         Ia, Ib = Ib, Ia
     torch.cuda.synchronize()
-    halo = 2 * steps
+    halo = 2 * steps * integrator          # PLM reach: two cells per stage
     sub = W.make_problem(cfg, sub=(tuple(o - halo for o in origin), tuple(m + 2 * halo for _ in range(3))))
+    sub.integrator = integrator
     Io, To, _, _, _ = oracle_run(sub, steps, dt)
     N = full.n
     ii = [(origin[a] + np.arange(m)) % N[a] for a in range(3)]
@@ -196,6 +198,12 @@ def test_c2_full_size_fp32_subbox():
     # checks a 16^3 block that contains beam cells and the periodic seam
     _full_vs_subbox("c2", rt.RT_F32, 2, (-4, 56, 56), 16, F32_I, F32_T,
                     "c2 full 128^3 fp32 2 steps, block 16^3")
+
+
+def test_c2_full_size_two_stage_fp32_subbox():
+    # the two-stage integrator on the tiled kernel at the benchmark's size
+    _full_vs_subbox("c2", rt.RT_F32, 2, (-4, 56, 56), 12, F32_I, F32_T,
+                    "c2 full 128^3 two-stage fp32 2 steps, block 12^3", integrator=2)
 
 
 def test_c2_full_size_fp64_subbox():
