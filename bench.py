@@ -168,11 +168,11 @@ def copy_bandwidth(dev, nbytes=1 << 30, reps=5):
     return 2 * nbytes / sec / 1e9
 
 
-def cpu_baseline(seconds):
+def cpu_baseline(seconds, threads=None):
     import torch
     from oracle import step as O
     from paper_2302_04283_amd import workloads as W
-    cores = len(os.sched_getaffinity(0))
+    cores = threads or len(os.sched_getaffinity(0))
     torch.set_num_threads(cores)
     m = 16
     sub = W.make_problem(CONFIG, sub=((56, 56, 56), (m, m, m)))
@@ -358,6 +358,9 @@ def main():
         print("[bench] context done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        # the same oracle on one host thread (a third of the sample time)
+        one = cpu_baseline(args.cpu_seconds / 3.0, threads=1)
+        out["cpu_baseline"]["one_thread"] = {"value": one["value"], "sample": one["sample"]}
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
