@@ -336,11 +336,13 @@ __global__ __launch_bounds__(kBlock) void k_step(RT_STEP_ARGS) {
     step_body<Real, NCH, EXT, ANG>(RT_STEP_PASS);
 }
 
-// The plain step of up to three direction chunks under a tighter register
-// budget: five waves per SIMD hide more of the latency of its neighbour and
-// geometry gathers (about 6% faster on the 128 x 64 x 128 Kerr-Schild grid).
+// The plain step of up to six direction chunks under a tighter register
+// budget (five waves per SIMD up to three chunks, four up to six): more waves
+// hide more of the latency of its neighbour and geometry gathers (about 6%
+// faster on the 128 x 64 x 128 x 162 Kerr-Schild grid, 12% on 256 x 128 x
+// 256 x 362).
 template <typename Real, int NCH, int ANG>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_step_lean(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NCH <= 3 ? 5 : 4))) void k_step_lean(
     RT_STEP_ARGS) {
     step_body<Real, NCH, false, ANG>(RT_STEP_PASS);
 }
@@ -457,7 +459,7 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
     case NC:                                                                                   \
         if (ext) {                                                                             \
             RT_LAUNCH_E(NC, true)                                                              \
-        } else if (NC <= 3 && G.ang_recon != 2) {                                              \
+        } else if (NC <= 6 && G.ang_recon != 2) {                                              \
             if (G.ang_recon == 1)                                                              \
                 hipLaunchKernelGGL((k_step_lean<Real, NC, 1>), dim3(nblk), dim3(kBlock), lds, s, \
                                    G, in, out, T, rho, u, ka, ks, dt, dT0, g->partials,        \
