@@ -225,8 +225,8 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the radiation step is built and timed on a "
-              "single MI355X (see DESIGN.md for how it would shard); --gpus %d is not "
-              "supported" % args.gpus, file=sys.stderr)
+              "single MI355X (sharding by space, with one halo exchange per step, is not "
+              "built); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

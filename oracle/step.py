@@ -33,7 +33,7 @@ n^0bar = u^0^ - u^.n^ (I_bar = I n0bar^4, dOmega_bar = dOmega/n0bar^2):
   I+_n = k_n I*_n + dt S / (4 pi d_n n0bar_n^3)
   dT0_a -= sum_n n^0 n_a (I+_n - I*_n) dOmega_n.
 
-Readings: masked bins carry zero intensity through the
+Readings where the paper leaves a choice: masked bins carry zero intensity through the
 coupling and are left out of its angle sums; the fixed beam cells are
 re-imposed after the coupling; the luminosity is the energy flux the scheme
 itself moves through the chosen boundary face.

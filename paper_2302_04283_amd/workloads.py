@@ -400,7 +400,9 @@ def make_problem(cfg: str, scale: Optional[tuple] = None,
                  recon: int = RECON_PLM) -> Problem:
     """Build one of the named workloads.
 
-    cfg:   'c1' .. 'c5' (see the design doc for the recipes).
+    cfg:   'c1' .. 'c5': Minkowski 16^3 x 42 (c1) and 128^3 x 162 with a beam
+           (c2); Kerr-Schild 128x64x128 x 162 (c3), 64x32x64 x 92 (c4) and
+           256x128x256 x 362 with an optically thick torus (c5).
     scale: override of the full-domain cell counts (n0, n1, n2); the recipe
            is otherwise unchanged (used for small parity cases).
     sub:   ((i0, i1, i2), (m0, m1, m2)) sub-box of the full domain; fields are

@@ -9,7 +9,7 @@ flat and the first in the neighbour order wins (the grid's symmetry makes
 exact ties, e.g. a direction whose neighbours are all masked).  The kernel's
 tolerance is 1e-10 in FP64 and 1e-5 in FP32, and the oracle is run with the
 same one.  A gap between two candidates right at the tolerance could still be
-judged differently by the two precisions, so the FP32 cases are kept to a
+decided differently by the two precisions, so the FP32 cases are kept to a
 few thousand cell-directions.
 """
 import math
