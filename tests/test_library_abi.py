@@ -68,3 +68,32 @@ def test_library_latlong_table_matches_oracle(nz, npsi):
     g = AG.build_latlong(nz, npsi)
     assert np.abs(nh - g.nhat).max() <= 1e-14
     assert np.abs(do - g.domega).max() <= 1e-14
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("latlong", (3, 5), b"latitude-longitude"),
+    ("latlong", (40, 16), b"latitude-longitude"),
+    ("ang_recon", 1, b"ang_recon"),
+    ("ang_recon", 3, b"ang_recon"),
+    ("integrator", 3, b"integrator"),
+    ("tau_coeff", -1.0, b"tau_coeff"),
+    ("rad_velocity", 2, b"rad_velocity"),
+])
+def test_option_validation_before_device_use(field, value, msg):
+    """Malformed scheme options are rejected by the descriptor check, before
+    any device call (so this runs without a GPU)."""
+    from paper_2302_04283_amd import workloads as W
+    p = W.make_problem("c3", scale=(4, 4, 4), nlev=1)
+    setattr(p, field, value)
+    with pytest.raises(rt.RtError):
+        rt.Grid(p, rt.RT_F64)
+    assert msg in rt.load().rt_last_error()
+
+
+def test_mapr_on_latlong_rejected_before_device_use():
+    from paper_2302_04283_amd import workloads as W
+    p = W.make_problem("c3", scale=(4, 4, 4), nlev=1)
+    p.latlong, p.ang_recon = (4, 8), 2
+    with pytest.raises(rt.RtError):
+        rt.Grid(p, rt.RT_F64)
+    assert b"ang_recon" in rt.load().rt_last_error()
