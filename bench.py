@@ -279,6 +279,11 @@ def main():
                      "avg_launch_s": avg},
         "no_root_events": st32["no_root"],
     }
+    tr = out["roofline"]["traffic"]
+    if tr:
+        # the measured HBM bytes over the same launch time, against the peak
+        out["roofline"]["traffic_GBs"] = tr / avg / 1e9
+        out["roofline"]["traffic_frac"] = tr / avg / 1e9 / HBM_PEAK_GBS
     if not args.no_fp64:
         wall64, per64, _ = time_path(prob, rt.RT_F64, K, args.warmup, dt, dev)
         print("[bench] fp64 done: %.3f ms/step" % (1e3 * wall64 / K), file=sys.stderr, flush=True)
