@@ -102,3 +102,23 @@ def test_latlong_plm_declines_adjoint():
         g.step_adjoint(I, cell, cell, u, cell, cell, 0.01, I.clone(), cell.clone(), I.clone(),
                        cell.clone(), I.clone())
     g.close()
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+def test_latlong_plm_with_two_stages_and_tau(prec):
+    """Angular PLM inside the extended kernel (two stages and the tau flux)."""
+    p = _problem("ks", (6, 12), 1)
+    p.integrator, p.tau_coeff = 2, 3.0
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    Io, To, dTo, Jo, _ = oracle_run(p, 3, dt)
+    Ig, Tg, dTg, Jg, g = gpu_run(p, prec, 3, dt)
+    g.close()
+    eI = rel_err(Ig, Io)
+    eT = float(np.max(np.abs(Tg - To) / To))
+    print("[latlong] plm + two stages + tau %s e_I=%.2e e_T=%.2e" % (
+        "fp64" if prec == rt.RT_F64 else "fp32", eI, eT), flush=True)
+    if prec == rt.RT_F64:
+        assert eI <= 1e-12 and eT <= 1e-13
+    else:
+        assert eI <= 1e-5 and eT <= 2e-7

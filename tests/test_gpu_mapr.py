@@ -80,3 +80,29 @@ def test_mapr_declines_adjoint_and_latlong():
     p.latlong = (4, 8)
     with pytest.raises(rt.RtError):
         rt.Grid(p, rt.RT_F64)
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+def test_mapr_with_two_stages_tau_and_substitute(prec):
+    """MAPR inside the extended kernel: two stages, the tau flux and the
+    velocity substitute together (Kerr-Schild, geodesic level 2)."""
+    p = _problem("ks", 2)
+    p.mapr_tie = 1e-10 if prec == rt.RT_F64 else 1e-5
+    p.integrator, p.tau_coeff, p.rad_velocity = 2, 3.0, 1
+    p.rho = p.rho * 1e-3
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    Io, To, dTo, Jo, _ = oracle_run(p, 3, dt)
+    Ig, Tg, dTg, Jg, g = gpu_run(p, prec, 3, dt)
+    g.close()
+    eI = rel_err(Ig, Io)
+    eT = float(np.max(np.abs(Tg - To) / To))
+    cv = p.kb_mu_mp / (p.gamma_gas - 1.0)
+    Erad = (np.asarray(p.initial_intensity()) * S.domega.numpy()).sum(-1)
+    cond = max(1.0, float(np.max(Erad / (p.rho * cv * p.T))))
+    print("[mapr] combined options %s e_I=%.2e e_T=%.2e (cond %.0f)" % (
+        "fp64" if prec == rt.RT_F64 else "fp32", eI, eT, cond), flush=True)
+    if prec == rt.RT_F64:
+        assert eI <= 1e-12 and eT <= 1e-13 * cond
+    else:
+        assert eI <= 1e-5 and eT <= 2e-7 * cond
