@@ -4,11 +4,15 @@
  * The library advances the gray, discrete-angle intensity of White et al.
  * (2023), "An Extension of the Athena++ Code Framework for Radiation-MHD in
  * General Relativity Using a Finite-Solid-Angle Discretization": the
- * conserved variable Q = n^0 n_0 I on a geodesic angular grid (Sec. 2.2,
- * gray integral form), moved by upwind spatial fluxes (Sec. 2.3-2.4) and
- * angular fluxes between neighbouring solid angles (Sec. 2.2, 2.6), then
- * coupled implicitly to a gamma-law gas through the fluid-frame quartic
- * (Sec. 2.5).
+ * conserved variable Q = n^0 n_0 I on a geodesic (or latitude-longitude)
+ * angular grid (Sec. 2.2, gray integral form, Sec. 2.6), moved by upwind
+ * spatial fluxes (Sec. 2.3-2.4) and angular fluxes between neighbouring
+ * solid angles (DC, MAPR or PLM face values), then coupled implicitly to a
+ * gamma-law gas through the fluid-frame quartic (Sec. 2.5); optionally with
+ * the two-stage integrator, the optical-depth-aware flux and the
+ * radiation-dominated velocity substitute.  rt_step_adjoint reverses the
+ * one-stage step; rt_gas_update hands the coupling's four-momentum to the
+ * gas.
  *
  * Conventions
  *   - Every call returns int: RT_OK (0) or a negative RT_E* code.  The
