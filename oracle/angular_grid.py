@@ -1,4 +1,4 @@
-"""Geodesic angular grid (paper Sec. 2.7, 'Angular Grids').
+"""Geodesic angular grid (paper Sec. 2.6, 'Angular Grids').
 
 The paper builds the grid in three steps: the 12 vertices of a regular
 icosahedron; each of the 20 faces split into N^2 equilateral triangles; the

@@ -15,7 +15,7 @@ Discrete update (gray integral form, Sec. 2.2), conserved Q = n^0 n_0 I per
 
   spatial upwind (Sec. 2.4): I_up = I_L if n^a > 0, I_R if n^a < 0, else 0;
   I_L, I_R from donor-cell or van Leer PLM per angle (Sec. 2.3);
-  angular flux through edge e = (lo, hi) of the geodesic grid (Sec. 2.7):
+  angular flux through edge e = (lo, hi) of the geodesic grid (Sec. 2.6):
   F_e = L_e (W(m_e) . nu_e) n_0(m_e) I_up, I_up = I_lo if W.nu > 0,
   I_hi if W.nu < 0; sigma = +1 for lo, -1 for hi.
 

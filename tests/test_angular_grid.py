@@ -1,4 +1,4 @@
-"""Pins of the oracle's geodesic angular grid (paper Sec. 2.7).
+"""Pins of the oracle's geodesic angular grid (paper Sec. 2.6).
 
 Each check is fixed by the paper or by geometry, not by the oracle itself:
 cell counts 10 N^2 + 2 with 12 pentagons (the paper's counts 12, 42, 92,
