@@ -101,6 +101,126 @@ __device__ __forceinline__ void group_sum_v(double (&x)[K]) {
     }
 }
 
+// Sums over aligned 32-lane groups of P pairs of values (x[2p], x[2p+1]) and
+// of S single values, in fewer instructions than group_sum_v: one
+// v_permlane16_swap of the pair leaves the first value's row-0 + row-1 sum in
+// row 0 and the second's in row 1, so one register carries both through the
+// four in-row levels; a swap of that register with itself then hands each
+// lane of the group both totals.  Every lane of a group receives bitwise
+// identical sums.
+__device__ __forceinline__ void split_d(double x, unsigned &lo, unsigned &hi) {
+    const unsigned long long b = __double_as_longlong(x);
+    lo = (unsigned)b;
+    hi = (unsigned)(b >> 32);
+}
+__device__ __forceinline__ double join_d(unsigned lo, unsigned hi) {
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int P, int S>
+__device__ __forceinline__ void group_sum32_pairs(double (&x)[2 * P], double (&y)[S > 0 ? S : 1]) {
+    double s[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        unsigned al, ah, bl, bh;
+        split_d(x[2 * p], al, ah);
+        split_d(x[2 * p + 1], bl, bh);
+        // first operand's odd rows <-> second operand's even rows
+        const auto L = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+        const auto H = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+        s[p] = join_d(L[0], H[0]) + join_d(L[1], H[1]);
+    }
+    constexpr int NS = S;
+#pragma unroll
+    for (int lvl = 0; lvl < 4; ++lvl) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (lvl == 0) s[p] += dpp_d<kDppXor1>(s[p]);
+            if (lvl == 1) s[p] += dpp_d<kDppXor2>(s[p]);
+            if (lvl == 2) s[p] += dpp_d<kDppHalfMirror>(s[p]);
+            if (lvl == 3) s[p] += dpp_d<kDppMirror>(s[p]);
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            if (lvl == 0) y[k] += dpp_d<kDppXor1>(y[k]);
+            if (lvl == 1) y[k] += dpp_d<kDppXor2>(y[k]);
+            if (lvl == 2) y[k] += dpp_d<kDppHalfMirror>(y[k]);
+            if (lvl == 3) y[k] += dpp_d<kDppMirror>(y[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) y[k] = swap_add<16>(y[k]);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        unsigned lo, hi;
+        split_d(s[p], lo, hi);
+        const auto L = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto H = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        x[2 * p] = join_d(L[0], H[0]);       // the total row 0 held
+        x[2 * p + 1] = join_d(L[1], H[1]);   // the total row 1 held
+    }
+}
+
+// Wavefront-wide (64-lane) sums of K values, four per register: a
+// v_permlane32_swap of two values leaves each one's half-sum in its own
+// wavefront half, a v_permlane16_swap of two such registers leaves the four
+// row sums in the four rows; the four in-row levels then run on one register
+// for four values, and two self-swaps (rows, then halves) hand every lane all
+// four totals.  K is padded to a multiple of four with zeros.  Every lane
+// receives bitwise identical sums.
+__device__ __forceinline__ void swap_pair(int dist, double a, double b, double &ra, double &rb) {
+    unsigned al, ah, bl, bh;
+    split_d(a, al, ah);
+    split_d(b, bl, bh);
+    if (dist == 16) {
+        const auto L = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+        const auto H = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+        ra = join_d(L[0], H[0]);
+        rb = join_d(L[1], H[1]);
+    } else {
+        const auto L = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
+        const auto H = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
+        ra = join_d(L[0], H[0]);
+        rb = join_d(L[1], H[1]);
+    }
+}
+template <int K>
+__device__ __forceinline__ void wave_sum_quads(double (&x)[K]) {
+    constexpr int Q = (K + 3) / 4;
+    double t[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = 4 * q + j < K ? x[4 * q + j] : 0.0;
+        double a0, a1, b0, b1;
+        swap_pair(32, v[0], v[1], a0, a1);   // half 0: v0, half 1: v1
+        swap_pair(32, v[2], v[3], b0, b1);   // half 0: v2, half 1: v3
+        const double s01 = a0 + a1, s23 = b0 + b1;
+        double c0, c1;
+        swap_pair(16, s01, s23, c0, c1);     // rows 0..3: v0, v2, v1, v3
+        t[q] = c0 + c1;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) t[q] += dpp_d<kDppXor1>(t[q]);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) t[q] += dpp_d<kDppXor2>(t[q]);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) t[q] += dpp_d<kDppHalfMirror>(t[q]);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) t[q] += dpp_d<kDppMirror>(t[q]);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double e, o;
+        swap_pair(16, t[q], t[q], e, o);     // e: rows 0/2 (v0 | v1), o: rows 1/3 (v2 | v3)
+        double r[4];
+        swap_pair(32, e, e, r[0], r[1]);
+        swap_pair(32, o, o, r[2], r[3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (4 * q + j < K) x[4 * q + j] = r[j];
+    }
+}
+
 template <int W>
 __device__ __forceinline__ int group_sum_i(int x) {
     static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "group width");

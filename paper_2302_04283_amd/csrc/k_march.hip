@@ -396,7 +396,13 @@ void k_march(
             kk[k] = Real(kn);
             gg[k] = Real(nb * dn * r * r);             // 1/(dn nb^3)
         }
-        {
+        if constexpr (SW == 32) {
+            double sp[2] = {Em, A1}, ss[1] = {A2};
+            group_sum32_pairs<1, 1>(sp, ss);
+            Em = sp[0];
+            A1 = sp[1];
+            A2 = ss[0] * (dt / kFourPi);
+        } else {
             double sf[3] = {Em, A1, A2};
             group_sum_v<SW, 3>(sf);
             Em = sf[0];
@@ -440,7 +446,12 @@ void k_march(
                 sm[2] = fma(dI, s_nh[NP + n], sm[2]);
                 sm[3] = fma(dI, s_nh[2 * NP + n], sm[3]);
             }
-            group_sum_v<SW, 4>(sm);
+            if constexpr (SW == 32) {
+                double none[1] = {0.0};
+                group_sum32_pairs<2, 0>(sm, none);
+            } else {
+                group_sum_v<SW, 4>(sm);
+            }
             if (a == 0) {
 #pragma unroll
                 for (int al = 0; al < 4; ++al)

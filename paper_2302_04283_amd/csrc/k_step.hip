@@ -200,7 +200,7 @@ __device__ __forceinline__ void step_body(DevGrid G, const Real *__restrict__ Ii
                 sv[6] = fma(Inb, ny, sv[6]);
                 sv[7] = fma(Inb, nz, sv[7]);
             }
-            group_sum_v<kWave, 8>(sv);
+            wave_sum_quads(sv);
             const double ug = rh * G.cv * Tm;
             if (sv[1] > 0.0 && sv[0] > rh + ug) {
                 const double iR = 1.0 / sv[1];
@@ -247,7 +247,7 @@ __device__ __forceinline__ void step_body(DevGrid G, const Real *__restrict__ Ii
             sf[1] = fma(n0 * nb2 * rr, Iw, sf[1]);
             sf[2] = fma(dom, nb * rr, sf[2]);
         }
-        group_sum_v<kWave, 3>(sf);
+        wave_sum_quads(sf);
         const double Em = sf[0], A1 = sf[1], A2 = sf[2] * (dts / kFourPi);
         const double B4 = A2 * aa * G.a_rad;
         const double B1 = rh * G.cv * (1.0 - A2 * as);
@@ -287,7 +287,7 @@ __device__ __forceinline__ void step_body(DevGrid G, const Real *__restrict__ Ii
             nr_acc += bad;
         }
         if (dT0) {
-            group_sum_v<kWave, 4>(sm);
+            wave_sum_quads(sm);
             if (lane == 0) {
                 const double *E0 = G.E0 + 16 * x.gc;
 #pragma unroll
