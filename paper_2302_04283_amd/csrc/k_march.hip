@@ -201,12 +201,16 @@ void k_march(
         hrow[j] = s_hrow[kHPG * cl + j];
         htest[j] = s_htest[kHPG * cl + j];
     }
-    // one fluid field per lane (a < 7): u1 u2 u3 rho kappa_a kappa_s T
+    // one fluid field per lane (a < 7): u1 u2 u3 rho kappa_a kappa_s T.  The
+    // lane's field address and stride are fixed here, so the plane loop keeps
+    // one address per lane instead of five scalar pointers.
+    const int fsel = a < 7 ? a : 6;
+    const double *fbase = fsel < 3 ? uvec + fsel
+                                   : (fsel == 3 ? rho : (fsel == 4 ? kap_a : (fsel == 5 ? kap_s : T)));
+    const long long fstride = fsel < 3 ? 3 : 1;
     auto load_fluid = [&](int z) -> double {
         const long long c = (long long)z * pcells + row;
-        const int f = a < 7 ? a : 6;
-        return f < 3 ? uvec[3 * c + f]
-                     : (f == 3 ? rho[c] : (f == 4 ? kap_a[c] : (f == 5 ? kap_s[c] : T[c])));
+        return fbase[fstride * c];
     };
 
     // first plane of the segment into LDS: own cell from the queue, two halo
