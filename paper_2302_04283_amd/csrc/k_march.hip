@@ -201,16 +201,23 @@ void k_march(
         hrow[j] = s_hrow[kHPG * cl + j];
         htest[j] = s_htest[kHPG * cl + j];
     }
-    // one fluid field per lane (a < 7): u1 u2 u3 rho kappa_a kappa_s T.  The
-    // lane's field address and stride are fixed here, so the plane loop keeps
-    // one address per lane instead of five scalar pointers.
+    // one fluid field per lane (a < 7): u1 u2 u3 rho kappa_a kappa_s T.  With
+    // FP32 intensities the lane's field address and stride are fixed here, so
+    // the plane loop keeps one address per lane instead of five scalar
+    // pointers (the scalar file is full); the FP64 kernel, at its VGPR limit,
+    // keeps the pointers and selects per plane.
     const int fsel = a < 7 ? a : 6;
     const double *fbase = fsel < 3 ? uvec + fsel
                                    : (fsel == 3 ? rho : (fsel == 4 ? kap_a : (fsel == 5 ? kap_s : T)));
     const long long fstride = fsel < 3 ? 3 : 1;
     auto load_fluid = [&](int z) -> double {
         const long long c = (long long)z * pcells + row;
-        return fbase[fstride * c];
+        if constexpr (sizeof(Real) == 4) {
+            return fbase[fstride * c];
+        } else {
+            return fsel < 3 ? uvec[3 * c + fsel]
+                            : (fsel == 3 ? rho[c] : (fsel == 4 ? kap_a[c] : (fsel == 5 ? kap_s[c] : T[c])));
+        }
     };
 
     // first plane of the segment into LDS: own cell from the queue, two halo
