@@ -98,10 +98,13 @@ enum { RT_BC_PERIODIC = 0, RT_BC_OUTFLOW_VACUUM = 1 };
  * rho + u_gas, the coupling runs at the velocity u'^a = (1 - f^a) u^a +
  * f^a u_rad^a instead of u: v_rad = R^{0a}/R^{00} (tetrad frame), the force
  * G^a = -(alpha_a a_rad T^4 + alpha_s E) u^a - alpha_E u_b R^{ab},
- * f^a = G^a dt / (u^0 (T_rad^{0a} - T_gas^{0a})) clamped to [0, 1] with
- * T^{0a} = (rho + u_gas + p) u^0 u^a at each velocity.  Cells with
- * R^{00} <= 0 or |v_rad| >= 1 keep u.  The velocity field itself is not
- * changed by rt_step (see rt_gas_update).
+ * f^a = G^a dt / (n^0 (T_rad^{0a} - T_gas^{0a})) clamped to [0, 1] with
+ * T^{0a} = (rho + u_gas + p) u^0 u^a at each velocity and n^0 = 1/lapse
+ * (the tetrad-frame time of a coordinate step dt is dt/n^0, so f^a is the
+ * share of the momentum gap one step of the force closes; the printed
+ * divisor u^a is read as this factor).  Cells with R^{00} <= 0 or
+ * |v_rad| >= 1 keep u.  The velocity field itself is not changed by rt_step
+ * (see rt_gas_update).
  * n_zeta, n_psi: with n_zeta > 0 the angular grid is the latitude-longitude
  * grid of Sec. 2.6 (nlev is ignored): n_zeta + 1 circles of latitude equally
  * spaced in cos(zeta) (zeta from the tetrad x^3 axis), n_psi + 1 meridians

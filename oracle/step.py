@@ -356,9 +356,18 @@ def radiation_velocity(Is: torch.Tensor, T: torch.Tensor, S: Setup, rho, u, ka, 
       u_b R^ab = -sum n^a n0bar I* dOmega,
     the momentum densities T_gas^0a = w u^0 u^a, T_rad^0a = w u_rad^0 u_rad^a
     (w = rho + u_gas + p), and the fraction per axis
-      f^a = clamp(G^a dt / (u^0 (T_rad^0a - T_gas^0a)), 0, 1)
+      f^a = clamp(G^a dt / (n^0 (T_rad^0a - T_gas^0a)), 0, 1)
     blends u^a -> (1 - f^a) u^a + f^a u_rad^a.  Other cells (and cells with
-    R^00 <= 0 or |v_rad| >= 1) keep u.  Masked bins are left out of the sums."""
+    R^00 <= 0 or |v_rad| >= 1) keep u.  Masked bins are left out of the sums.
+
+    The factor n^0 = 1/alpha (the normal observer's n^0, Sec. 2.2): the
+    coupling's operator-split momentum equation d_0 T^0_alpha = G_alpha with a
+    stationary tetrad makes the gas's tetrad-frame momentum change by
+    G^a dt / n^0 over a coordinate step dt (the coupling's own implicit
+    factors run over the same dt / n^0), so f^a is the share of the gap
+    T_rad^0a - T_gas^0a that one step of the force closes.  (The printed
+    divisor u^a is singular for gas at rest and changes sign with the
+    direction of motion; see the design notes.)"""
     prob = S.prob
     cv = prob.kb_mu_mp / (prob.gamma_gas - 1.0)
     u0 = torch.sqrt(1.0 + (u * u).sum(-1))
@@ -381,7 +390,8 @@ def radiation_velocity(Is: torch.Tensor, T: torch.Tensor, S: Setup, rho, u, ka, 
     ur = ur0[..., None] * v
     G = (-(aa * prob.a_rad * T ** 4 + as_ * Em)[..., None] * u - (aa + as_)[..., None] * uR)
     gap = (w * ur0)[..., None] * ur - (w * u0)[..., None] * u
-    den = u0[..., None] * gap
+    n0 = S.n_up_c[..., 0, 0]                    # e^0_0^, the same for every direction
+    den = n0[..., None] * gap
     f = torch.where(den != 0.0, G * dt / torch.where(den != 0.0, den, torch.ones_like(den)),
                     torch.zeros_like(den)).clamp(0.0, 1.0)
     us = (1.0 - f) * u + f * ur

@@ -217,7 +217,7 @@ __device__ __forceinline__ void step_body(DevGrid G, const Real *__restrict__ Ii
                     for (int a = 0; a < 3; ++a) {
                         const double ura = ur0 * vr[a];
                         const double Ga = -emit * uo[a] + (aa + as) * sv[5 + a];
-                        const double den = u0 * (wg * ur0 * ura - wg * u0 * uo[a]);
+                        const double den = n0 * (wg * ur0 * ura - wg * u0 * uo[a]);
                         double f = den != 0.0 ? Ga * dts / den : 0.0;
                         f = fmin(fmax(f, 0.0), 1.0);
                         un[a] = (1.0 - f) * uo[a] + f * ura;
