@@ -222,6 +222,28 @@ int rt_step(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
             const double *kappa_s, double dt, double *dT0, double *lum, void *I_star);
 
 /*
+ * rt_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, the same kernels and bit-identical results, but the
+ * per-block partial sums that rt_step leaves in the grid's buffer for its
+ * final fixed-order reduction (luminosity, masked energy, quartic failures)
+ * go to a static device array of the library instead: 16 MiB per GPU,
+ * present on every GPU the library runs on until the process ends.  The
+ * call allocates nothing and frees nothing.
+ *   Limit: 2 doubles + 1 int per workgroup of the step's largest launch;
+ *   a grid whose step needs more (more than about 13 million cells on the
+ *   general kernel) is rejected with RT_EINVAL before any launch.
+ *   All calls on one GPU share that array (every block rewrites its own
+ *   slots before they are read, so nothing carries over from a previous
+ *   call); calls that overlap on one GPU, on any streams or grids, race.
+ *   RT_EDEVICE if the array's device address could not be looked up when
+ *   the grid was built.
+ */
+int rt_step_noalloc(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
+                    const double *rho, const double *u_tet, const double *kappa_a,
+                    const double *kappa_s, double dt, double *dT0, double *lum, void *I_star);
+
+/*
  * Adjoint of rt_step for the functional J = sum over steps of
  * w_s * dt * l(I_s), l the luminosity of rt_step.  Given the state at the
  * start of step s (I_n, T_n, the same fluid, opacities and dt) and

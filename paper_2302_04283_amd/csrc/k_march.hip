@@ -523,7 +523,8 @@ void k_march(
 template <typename Real, int SW, int NC, bool STG = false>
 int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                const double *rho, const double *u, const double *ka, const double *ks,
-               double dt, double *dT0, Real *Istar, const MStage<Real> &st = MStage<Real>{}) {
+               double dt, double *dT0, Real *Istar, const Partials &P,
+               const MStage<Real> &st = MStage<Real>{}) {
     const MarchInfo &M = g->march;
     static bool lds_set = false;   // one attribute call per instantiation
     if (!lds_set) {
@@ -535,7 +536,7 @@ int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T
     }
     hipLaunchKernelGGL((k_march<Real, SW, NC, STG>), dim3(M.grid), dim3(kTC * SW), M.lds, s,
                        g->dg, M, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho,
-                       u, ka, ks, dt, dT0, g->partials, g->noroot_partial, Istar, st);
+                       u, ka, ks, dt, dT0, P.sums, P.noroot, Istar, st);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
 }
 
@@ -545,20 +546,20 @@ int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T
 template <typename Real>
 int march_rk2_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                 const double *rho, const double *u, const double *ka, const double *ks,
-                double dt, double *dT0, double *lum) {
+                double dt, double *dT0, double *lum, const Partials &P) {
     const size_t ncell = (size_t)g->dg.n0 * g->dg.n1 * g->dg.n2;
     if (hipMemcpyAsync(g->stage_T, T, ncell * sizeof(double), hipMemcpyDeviceToDevice, s) !=
         hipSuccess)
         return RT_EDEVICE;
     const MStage<Real> s1{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 0.5};
     int rc = launch_one<Real, 32, 6, true>(g, s, Iin, g->stage_I, g->stage_T, rho, u, ka, ks, dt,
-                                           dT0, nullptr, s1);
-    if (rc == RT_OK) rc = launch_finalize(g, s, g->march.grid, 0.5 * dt, lum);
+                                           dT0, nullptr, P, s1);
+    if (rc == RT_OK) rc = launch_finalize(g, s, g->march.grid, 0.5 * dt, lum, P);
     if (rc != RT_OK) return rc;
     const MStage<Real> s2{static_cast<const Real *>(Iin), g->stage_T, 0.5, 0.5, 0.5, 0.5, 0.5, 1.0};
     rc = launch_one<Real, 32, 6, true>(g, s, g->stage_I, Iout, T, rho, u, ka, ks, dt, dT0, nullptr,
-                                       s2);
-    if (rc == RT_OK) rc = launch_finalize(g, s, g->march.grid, 0.5 * dt, lum);
+                                       P, s2);
+    if (rc == RT_OK) rc = launch_finalize(g, s, g->march.grid, 0.5 * dt, lum, P);
     return rc;
 }
 
@@ -568,11 +569,11 @@ bool march_rk2_config(int sw, int nc) { return sw == 32 && nc == 6; }
 
 int launch_march_rk2(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                      const double *rho, const double *u, const double *ka, const double *ks,
-                     double dt, double *dT0, double *lum) {
+                     double dt, double *dT0, double *lum, const Partials &P) {
     if (!march_rk2_config(g->march.sw, g->march.nc)) return RT_EINVAL;
     if (g->precision == RT_F32)
-        return march_rk2_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
-    return march_rk2_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+        return march_rk2_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);
+    return march_rk2_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);
 }
 
 // Lane-group width and directions per lane for each supported direction count.
@@ -622,12 +623,12 @@ size_t march_lds_bytes(int precision, int nang, int np) {
 
 int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                  const double *rho, const double *u, const double *ka, const double *ks,
-                 double dt, double *dT0, void *Istar) {
+                 double dt, double *dT0, void *Istar, const Partials &P) {
     const MarchInfo &M = g->march;
 #define RT_CASE(R, SW, NC)                                                                    \
     if (M.sw == SW && M.nc == NC)                                                             \
         return launch_one<R, SW, NC>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0,          \
-                                     static_cast<R *>(Istar));
+                                     static_cast<R *>(Istar), P);
     if (g->precision == RT_F32) {
         RT_CASE(float, 16, 1)
         RT_CASE(float, 16, 3)

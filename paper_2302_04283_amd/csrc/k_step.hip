@@ -11,10 +11,25 @@
 // results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "k_transport.h"
 
 namespace rt {
 namespace {
+
+// Per-block partial sums of rt_step_noalloc: a file-scope device array, one
+// copy on every GPU the library runs on, held until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in); it looks up each device's address once and passes that.  Every
+// block writes its own slots before the finaliser reads them, so nothing has
+// to be cleared between calls; calls that overlap on one GPU share the array
+// and race.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kScratchDevices] = {};
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
@@ -436,7 +451,7 @@ template <typename Real>
 int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                   const double *rho, const double *u, const double *ka, const double *ks,
                   double dt, double *dT0, double *lum, void *Istar, const Stage<Real> &st,
-                  double lum_dt) {
+                  double lum_dt, const Partials &P) {
     const DevGrid &G = g->dg;
     const int nblk = step_blocks(g);
     const int nch = (G.nang + kWave - 1) / kWave;
@@ -446,7 +461,7 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
     const size_t lds = G.ang_recon == 2 ? (size_t)kWavesPerBlock * 2 * G.nang * sizeof(Real) : 0;
 #define RT_LAUNCH_A(NC, E, A)                                                                  \
     hipLaunchKernelGGL((k_step<Real, NC, E, A>), dim3(nblk), dim3(kBlock), lds, s, G, in, out,    \
-                       T, rho, u, ka, ks, dt, dT0, g->partials, g->noroot_partial,             \
+                       T, rho, u, ka, ks, dt, dT0, P.sums, P.noroot,                           \
                        static_cast<Real *>(Istar), st)
 #define RT_LAUNCH_E(NC, E)                                                                     \
     if (G.ang_recon == 2)                                                                      \
@@ -462,12 +477,12 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
         } else if (NC <= 6 && G.ang_recon != 2) {                                              \
             if (G.ang_recon == 1)                                                              \
                 hipLaunchKernelGGL((k_step_lean<Real, NC, 1>), dim3(nblk), dim3(kBlock), lds, s, \
-                                   G, in, out, T, rho, u, ka, ks, dt, dT0, g->partials,        \
-                                   g->noroot_partial, static_cast<Real *>(Istar), st);         \
+                                   G, in, out, T, rho, u, ka, ks, dt, dT0, P.sums,             \
+                                   P.noroot, static_cast<Real *>(Istar), st);                  \
             else                                                                               \
                 hipLaunchKernelGGL((k_step_lean<Real, NC, 0>), dim3(nblk), dim3(kBlock), lds, s, \
-                                   G, in, out, T, rho, u, ka, ks, dt, dT0, g->partials,        \
-                                   g->noroot_partial, static_cast<Real *>(Istar), st);         \
+                                   G, in, out, T, rho, u, ka, ks, dt, dT0, P.sums,             \
+                                   P.noroot, static_cast<Real *>(Istar), st);                  \
         } else {                                                                               \
             RT_LAUNCH_E(NC, false)                                                             \
         }                                                                                      \
@@ -488,7 +503,7 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
 #undef RT_LAUNCH_A
 #undef RT_LAUNCH_E
     if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
-    return launch_finalize(g, s, nblk, lum_dt, lum);
+    return launch_finalize(g, s, nblk, lum_dt, lum, P);
 }
 
 // The two-stage (Heun) step: stage 1 into the grid's stage buffers, stage 2
@@ -496,18 +511,18 @@ int launch_step_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double
 template <typename Real>
 int launch_rk2_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                  const double *rho, const double *u, const double *ka, const double *ks,
-                 double dt, double *dT0, double *lum) {
+                 double dt, double *dT0, double *lum, const Partials &P) {
     const size_t ncell = (size_t)g->dg.n0 * g->dg.n1 * g->dg.n2;
     if (hipMemcpyAsync(g->stage_T, T, ncell * sizeof(double), hipMemcpyDeviceToDevice, s) !=
         hipSuccess)
         return RT_EDEVICE;
     const Stage<Real> s1{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 0.5};
     int rc = launch_step_t<Real>(g, s, Iin, g->stage_I, g->stage_T, rho, u, ka, ks, dt, dT0, lum,
-                                 nullptr, s1, 0.5 * dt);
+                                 nullptr, s1, 0.5 * dt, P);
     if (rc != RT_OK) return rc;
     const Stage<Real> s2{static_cast<const Real *>(Iin), g->stage_T, 0.5, 0.5, 0.5, 0.5, 0.5, 1.0};
     return launch_step_t<Real>(g, s, g->stage_I, Iout, T, rho, u, ka, ks, dt, dT0, lum, nullptr,
-                               s2, 0.5 * dt);
+                               s2, 0.5 * dt, P);
 }
 
 }  // namespace
@@ -517,32 +532,53 @@ int step_blocks(const rt_grid *g) {
     return (int)((ncell + kCellsPerBlock - 1) / kCellsPerBlock);
 }
 
-int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *lum) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, g->partials, g->noroot_partial,
-                       nblocks, dt, lum, g->ledger, g->noroot);
+int step_partial_blocks(const rt_grid *g) {
+    return g->march.enabled ? g->march.grid : step_blocks(g);
+}
+
+int scratch_address(void **ptr, size_t *bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return RT_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RT_EDEVICE;
+        g_scratch_addr[dev] = p;
+    }
+    *ptr = g_scratch_addr[dev];
+    *bytes = kScratchBytes;
+    return RT_OK;
+}
+
+int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *lum,
+                    const Partials &P) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, P.sums, P.noroot, nblocks, dt,
+                       lum, g->ledger, g->noroot);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
 }
 
 int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                 const double *rho, const double *u, const double *ka, const double *ks,
-                double dt, double *dT0, double *lum, void *Istar) {
+                double dt, double *dT0, double *lum, void *Istar, const Partials &P) {
     if (g->march.enabled && g->integrator == 2)
-        return launch_march_rk2(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+        return launch_march_rk2(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);
     if (g->march.enabled) {
-        int rc = launch_march(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar);
+        int rc = launch_march(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
         if (rc != RT_OK) return rc;
-        return launch_finalize(g, s, g->march.grid, dt, lum);
+        return launch_finalize(g, s, g->march.grid, dt, lum, P);
     }
     if (g->integrator == 2) {
         if (g->precision == RT_F32)
-            return launch_rk2_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
-        return launch_rk2_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum);
+            return launch_rk2_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);
+        return launch_rk2_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);
     }
     if (g->precision == RT_F32)
         return launch_step_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, Istar,
-                                    Stage<float>{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0}, dt);
+                                    Stage<float>{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0}, dt,
+                                    P);
     return launch_step_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, Istar,
-                                 Stage<double>{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0}, dt);
+                                 Stage<double>{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0}, dt,
+                                 P);
 }
 
 int launch_moments(rt_grid *g, hipStream_t s, const void *I, const double *u, double *R,

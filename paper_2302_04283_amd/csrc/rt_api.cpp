@@ -316,6 +316,17 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
                 }
             }
         }
+        // this device's static scratch for rt_step_noalloc (looked up once per
+        // device, with the device current); a failed lookup leaves it unset and
+        // only that entry point reports it
+        {
+            void *sp = nullptr;
+            size_t sb = 0;
+            if (rt::scratch_address(&sp, &sb) == RT_OK) {
+                g->scratch = sp;
+                g->scratch_bytes = sb;
+            }
+        }
         g->max_blocks = std::max(rt::step_blocks(g), g->march.enabled ? g->march.grid : 0);
         g->partials = up.zeros<double>((size_t)g->max_blocks * 2);
         g->noroot_partial = up.zeros<int>((size_t)g->max_blocks);
@@ -437,7 +448,43 @@ int rt_step(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
     (void)hipGetDevice(&cur);
     if (cur != g->device) (void)hipSetDevice(g->device);
     int rc = rt::launch_step(g, (hipStream_t)stream, I_in, I_out, T, rho, u_tet, kappa_a, kappa_s,
-                             dt, dT0, lum, I_star);
+                             dt, dT0, lum, I_star, rt::Partials{g->partials, g->noroot_partial});
+    if (cur != g->device) (void)hipSetDevice(cur);
+    if (rc != RT_OK) return fail(rc, "kernel launch failed");
+    return RT_OK;
+}
+
+int rt_step_noalloc(rt_grid *g, void *stream, const void *I_in, void *I_out, double *T,
+                    const double *rho, const double *u_tet, const double *kappa_a,
+                    const double *kappa_s, double dt, double *dT0, double *lum, void *I_star) {
+    if (!g) return fail(RT_EINVAL, "grid is NULL");
+    if (!I_in || !I_out || !T || !rho || !u_tet || !kappa_a || !kappa_s)
+        return fail(RT_EINVAL, "NULL state pointer");
+    if (I_in == I_out) return fail(RT_EINVAL, "I_out must not alias I_in");
+    if (I_star && (I_star == I_in || I_star == I_out))
+        return fail(RT_EINVAL, "I_star must not alias I_in or I_out");
+    if (I_star && (g->integrator == 2 || g->dg.tau_coeff > 0.0))
+        return fail(RT_EINVAL, "I_star needs the one-stage step without the optical-depth-aware flux");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RT_EINVAL, "dt must be positive and finite");
+    if (!g->scratch) return fail(RT_EDEVICE, "the device's static scratch could not be located");
+    // layout: [blocks][2] doubles, then [blocks] ints from the next 256-byte boundary
+    const size_t nb = (size_t)rt::step_partial_blocks(g);
+    const size_t off = (nb * 2 * sizeof(double) + 255) / 256 * 256;
+    const size_t need = off + nb * sizeof(int);
+    if (need > g->scratch_bytes) {
+        std::ostringstream m;
+        m << "rt_step_noalloc: this grid's step writes partial sums of " << nb << " blocks ("
+          << need << " bytes), more than the static scratch holds (" << g->scratch_bytes
+          << " bytes); use rt_step";
+        return fail(RT_EINVAL, m.str());
+    }
+    unsigned char *base = static_cast<unsigned char *>(g->scratch);
+    const rt::Partials P{reinterpret_cast<double *>(base), reinterpret_cast<int *>(base + off)};
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    int rc = rt::launch_step(g, (hipStream_t)stream, I_in, I_out, T, rho, u_tet, kappa_a, kappa_s,
+                             dt, dT0, lum, I_star, P);
     if (cur != g->device) (void)hipSetDevice(cur);
     if (rc != RT_OK) return fail(rc, "kernel launch failed");
     return RT_OK;

@@ -101,6 +101,14 @@ struct DevGrid {
     double beam_I;
 };
 
+// Where a step's kernels leave their per-block partial sums (luminosity,
+// masked energy, quartic failures) for the finaliser: the grid's own buffer,
+// or the device-static scratch of rt_step_noalloc.
+struct Partials {
+    double *sums;                 // [blocks][2]
+    int *noroot;                  // [blocks]
+};
+
 // Fast path for spatially uniform geometry (k_march.hip).
 struct MarchInfo {
     int enabled;
@@ -128,6 +136,8 @@ struct rt_grid {
     std::vector<double> host_vw;  // [G][nedge][2]
     std::vector<void *> allocs;   // every device allocation
     // scratch
+    void *scratch = nullptr;      // this device's static scratch (rt_step_noalloc)
+    size_t scratch_bytes = 0;
     double *partials = nullptr;   // [max_blocks][2]
     int *noroot_partial = nullptr;// [max_blocks]
     double *ledger = nullptr;     // [1] masked energy
@@ -142,21 +152,27 @@ struct rt_grid {
 namespace rt {
 int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                 const double *rho, const double *u, const double *ka, const double *ks,
-                double dt, double *dT0, double *lum, void *Istar);
+                double dt, double *dT0, double *lum, void *Istar, const Partials &P);
 int launch_moments(rt_grid *g, hipStream_t s, const void *I, const double *u,
                    double *R, double *R0, double *E);
 int step_blocks(const rt_grid *g);
+// blocks whose partial sums one step writes (the largest launch of the step)
+int step_partial_blocks(const rt_grid *g);
+// device address of this device's static scratch (the calling thread's
+// current device); looked up once per device
+int scratch_address(void **ptr, size_t *bytes);
 bool march_config(int precision, int nang, int &sw, int &nc);
 size_t march_lds_bytes(int precision, int nang, int np);
 int march_pstride(int precision, int nang);
 int launch_march(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                  const double *rho, const double *u, const double *ka, const double *ks,
-                 double dt, double *dT0, void *Istar);
-int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *lum);
+                 double dt, double *dT0, void *Istar, const Partials &P);
+int launch_finalize(rt_grid *g, hipStream_t s, int nblocks, double dt, double *lum,
+                    const Partials &P);
 bool march_rk2_config(int sw, int nc);
 int launch_march_rk2(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                      const double *rho, const double *u, const double *ka, const double *ks,
-                     double dt, double *dT0, double *lum);
+                     double dt, double *dT0, double *lum, const Partials &P);
 int launch_adjoint(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
                    const double *rho, const double *u, const double *ka, const double *ks,
                    double dt, double lum_weight, const void *lamI1, const double *lamT1,

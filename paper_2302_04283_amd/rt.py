@@ -81,6 +81,7 @@ def load():
     lib.rt_angles.argtypes = [vp, _dp, _dp]
     lib.rt_max_dt.argtypes = [vp, C.c_double, _dp]
     lib.rt_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp, vp]
+    lib.rt_step_noalloc.argtypes = lib.rt_step.argtypes
     lib.rt_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.rt_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double,
                                     vp, vp, vp, vp, vp, vp, vp, vp]
@@ -91,7 +92,7 @@ def load():
     lib.rt_free.restype = None
     lib.rt_last_error.restype = C.c_char_p
     for f in ("rt_init_grid", "rt_geodesic_angles", "rt_grid_info", "rt_angles",
-              "rt_max_dt", "rt_step", "rt_moments", "rt_stats", "rt_step_adjoint",
+              "rt_max_dt", "rt_step", "rt_step_noalloc", "rt_moments", "rt_stats", "rt_step_adjoint",
               "rt_gas_update", "rt_latlong_angles"):
         getattr(lib, f).restype = C.c_int
     _LIB = lib
@@ -243,7 +244,9 @@ class Grid:
 
     # -------------------------------------------------------------- compute
     def step(self, I_in, I_out, T, rho, u, kappa_a, kappa_s, dt, dT0=None, lum=None,
-             stream=None, I_star=None):
+             stream=None, I_star=None, noalloc=False):
+        """rt_step, or with ``noalloc`` rt_step_noalloc (the same step with its
+        partial sums in the library's static device scratch)."""
         import torch
         rd = self.real_dtype()
         f8 = torch.float64
@@ -258,9 +261,10 @@ class Grid:
         self._need(lum, (1,), f8, "lum")
         self._need(I_star, self._state_shape(), rd, "I_star")
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
-        _check(self._lib.rt_step(self._h, C.c_void_p(s.cuda_stream), _dev(I_in), _dev(I_out),
-                                 _dev(T), _dev(rho), _dev(u), _dev(kappa_a), _dev(kappa_s),
-                                 float(dt), _dev(dT0), _dev(lum), _dev(I_star)))
+        fn = self._lib.rt_step_noalloc if noalloc else self._lib.rt_step
+        _check(fn(self._h, C.c_void_p(s.cuda_stream), _dev(I_in), _dev(I_out), _dev(T), _dev(rho),
+                  _dev(u), _dev(kappa_a), _dev(kappa_s), float(dt), _dev(dT0), _dev(lum),
+                  _dev(I_star)))
 
     def step_adjoint(self, I_n, T_n, rho, u, kappa_a, kappa_s, dt, lamI_next, lamT_next,
                      lamI_out, lamT_out, work, grad_kappa_a=None, grad_kappa_s=None,

@@ -35,6 +35,8 @@ def test_host_error_paths():
     assert lib.rt_geodesic_angles(0, None, None) == rt.RT_EINVAL
     assert lib.rt_step(None, None, None, None, None, None, None, None, None, 0.1, None,
                        None, None) == rt.RT_EINVAL
+    assert lib.rt_step_noalloc(None, None, None, None, None, None, None, None, None, 0.1, None,
+                               None, None) == rt.RT_EINVAL
     assert lib.rt_step_adjoint(None, None, None, None, None, None, None, None, 0.1, 1.0,
                                None, None, None, None, None, None, None, None) == rt.RT_EINVAL
     assert lib.rt_gas_update(None, None, None, None, None, None, None, None) == rt.RT_EINVAL
