@@ -8,7 +8,9 @@ more than the 53 bits of a double need) and finishes with one Newton step.
 
 Edge cases (the paper is silent): B4 = 0 gives the linear root -B0/B1;
 B0 >= 0 or a non-finite coefficient has no positive root, in which case the
-result is 1e-12 and the cell is counted.
+result is 1e-12 and the cell is counted.  A root that over- or underflows
+the double range (outside (0, 1e300): coefficients near its ends) is no
+usable temperature either and takes the same floor, counted.
 
 The backward pass uses the implicit-function theorem:
 dT/dB_k = -T^k / (4 B4 T^3 + B1), k = 4, 1, 0.
@@ -43,6 +45,7 @@ def _solve(B4, B1, B0):
     dp = 4.0 * B4 * T ** 3 + B1
     T = T - p / dp
     T = torch.where(B4 > 0, T, lin)
+    ok = ok & (T > 0) & (T < 1e300)
     nbad = int((~ok).sum())
     T = torch.where(ok, T, torch.full_like(T, NO_ROOT_T))
     return T, nbad

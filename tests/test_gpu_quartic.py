@@ -1,0 +1,125 @@
+"""The device quartic (Sec. 2.5) through rt_step against the oracle's root
+over the stiffness range: per cell B4/B1 spans 24 decades (rho from 1e-12
+to 1e12 at absorption optical depths 1e-3..1e2 per step), cells without
+absorption (B4 = 0), cells whose scattering in a moving fluid leaves no
+positive root (B0 >= 0), and a cell whose root overflows the double range
+(rho = 1e-300): the last two take the floor T = 1e-12 and are counted.
+
+In the sweep the radiation field is empty: the gas cools by emission alone,
+B0 = -B1 T-, and the coefficients differ between the two sides only by the
+summation order of A2 (positive terms), so T+ agrees to a few ulp: the
+quartic is well conditioned in its coefficients (|B0| / (T P'(T)) <= 1).
+With radiation present, B0 carries the difference A1 - E-, which cancels
+when the optical depth is small; that case is covered by the end-to-end
+parity tests at their tolerances.  The no-root and overflow cases share one
+radiation field across the grid, so the transport is exactly zero.  Both
+the tiled kernel (n0, n1 multiples of 4) and the general kernel run every
+case, in FP64.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import step as O
+from paper_2302_04283_amd import rt
+from paper_2302_04283_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ULP = 2.0 ** -52
+
+
+def _grid(n):
+    return W.make_custom("minkowski_cart", n, [(0.0, 1.0)] * 3, 2,
+                         [(W.BC_PERIODIC, W.BC_PERIODIC)] * 3)
+
+
+def _run_both(p, I_dir, dt):
+    """One step of the same problem on both sides: (T_gpu, T_ora, no-root
+    counts, fast_path).  I_dir: intensity per direction, the same in every cell."""
+    S = O.setup(p)
+    I0 = np.broadcast_to(I_dir, (p.n[2], p.n[1], p.n[0], p.nang)).copy()
+    stats = {}
+    rho, u, ka, ks = O.fluid_tensors(p)
+    Is, _ = O.transport(torch.as_tensor(I0), S, dt)
+    assert float((Is - torch.as_tensor(I0)).abs().max()) == 0.0     # no transport
+    _, To, _ = O.coupling(Is, torch.as_tensor(p.T), S, rho, u, ka, ks, dt, stats)
+    dev = torch.device("cuda", 0)
+    g = rt.Grid(p, rt.RT_F64)
+    Ia = torch.as_tensor(I0).to(dev)
+    Ib = torch.empty_like(Ia)
+    T = torch.as_tensor(p.T).to(dev)
+    f = [torch.as_tensor(x).to(dev) for x in (p.rho, p.u_tet, p.kappa_a, p.kappa_s)]
+    g.step(Ia, Ib, T, f[0], f[1], f[2], f[3], dt)
+    torch.cuda.synchronize()
+    nr = g.stats()["no_root"]
+    fast = g.fast_path
+    g.close()
+    return T.cpu().numpy(), To.numpy(), nr, stats.get("no_root", 0), fast
+
+
+@pytest.mark.parametrize("n", [(8, 8, 4), (6, 6, 4)])
+def test_quartic_stiffness_sweep(n):
+    p = _grid(n)
+    dt = 0.01
+    rng = np.random.default_rng(17)
+    shp = p.T.shape
+    rho = 10.0 ** rng.uniform(-12, 12, shp)
+    tau = 10.0 ** rng.uniform(-3, 2, shp)
+    p.rho = rho
+    p.kappa_a = tau / (rho * dt)
+    p.kappa_a.reshape(-1)[:8] = 0.0               # B4 = 0: T unchanged
+    p.T = 10.0 ** rng.uniform(-2, 2, shp)
+    I = np.zeros(p.nang)                          # empty radiation field
+    Tg, To, nr_g, nr_o, fast = _run_both(p, I, dt)
+    assert fast == (n[0] % 4 == 0)
+    cv = p.kb_mu_mp / (p.gamma_gas - 1.0)
+    ratio = (tau / (1 + tau)) * p.a_rad / (rho * cv)
+    assert ratio.min() < 1e-10 and ratio.max() > 1e10   # the span of B4/B1
+    rel = np.abs(Tg - To) / To
+    print("[quartic] %s %s: max |dT|/T = %.1f ulp, no-root %d / %d" % (
+        n, "tiled" if fast else "general", rel.max() / ULP, nr_g, nr_o), flush=True)
+    assert nr_g == nr_o == 0
+    assert rel.max() <= 8 * ULP
+    # no absorption: B4 = 0, the linear root -B0/B1 = T- up to the rounding of B1 T- / B1
+    flat = p.kappa_a.reshape(-1) == 0.0
+    assert np.abs(Tg.reshape(-1)[flat] / p.T.reshape(-1)[flat] - 1.0).max() <= 2 * ULP
+
+
+@pytest.mark.parametrize("n", [(8, 8, 4), (6, 6, 4)])
+def test_quartic_no_root_and_overflow_take_the_floor(n):
+    # scattering only, fluid moving at 0.6 c along x^1; radiation beamed
+    # along the motion (exp(5 n^1): the coupling asks more energy of the gas
+    # than it holds, B0 >= 0) or against it (exp(-2 n^1): the gas gains
+    # energy, and with rho = 1e-300 its temperature overflows)
+    dt = 0.1
+    out = {}
+    for beam in (5.0, -2.0):
+        p = _grid(n)
+        S = O.setup(p)
+        I = np.exp(beam * S.nhat[:, 0].numpy())
+        p.u_tet[..., 0] = 0.6
+        p.kappa_a[:] = 0.0
+        rho = np.ones(p.T.shape)
+        # one cell at rho = 1e-300, the rest at rho = 1 (alpha_s = 3 / dt everywhere)
+        rho.reshape(-1)[5] = 1e-300
+        p.rho = rho
+        p.kappa_s = 3.0 / (dt * rho)
+        Tg, To, nr_g, nr_o, fast = _run_both(p, I, dt)
+        out[beam] = (Tg, To, nr_g, nr_o)
+        floor_g = Tg.reshape(-1) == 1e-12
+        floor_o = To.reshape(-1) == 1e-12
+        print("[quartic] %s beam %+.0f: floored %d (gpu) / %d (oracle), no-root %d / %d" % (
+            n, beam, floor_g.sum(), floor_o.sum(), nr_g, nr_o), flush=True)
+        assert np.array_equal(floor_g, floor_o)
+        assert nr_g == nr_o == int(floor_g.sum())
+        ok = ~floor_o
+        if ok.any():
+            rel = np.abs(Tg.reshape(-1)[ok] - To.reshape(-1)[ok]) / To.reshape(-1)[ok]
+            assert rel.max() <= 1e-13
+    # beamed along the motion: every cell has no root; against it only the
+    # rho = 1e-300 cell overflows
+    assert out[5.0][2] == p.T.size
+    assert out[-2.0][2] == 1 and out[-2.0][0].reshape(-1)[5] == 1e-12
