@@ -265,6 +265,34 @@ def _van_leer_slope(a, b, c):
     return torch.where(pos, 2.0 * prod / den, torch.zeros_like(dm))
 
 
+def mapr_candidates(I: torch.Tensor, S: Setup):
+    """MAPR candidate planes of every cell-direction (Sec. 2.6): the gradient
+    in the tangent plane of the plane through the direction and each pair of
+    consecutive neighbours, and its squared norm (inf for padding slots).
+    Returns (cand [.., N, 6, 2], n2 [.., N, 6])."""
+    nbr, nxt, inv, valid, _, _ = S.mapr
+    dI = I[..., nbr] - I[..., None]                          # [.., N, 6]
+    dJ = torch.gather(dI, -1, nxt.expand(dI.shape))
+    cand = torch.einsum("nikl,...nil->...nik", inv, torch.stack([dI, dJ], -1))
+    n2 = torch.where(valid, (cand * cand).sum(-1), torch.full_like(dI, math.inf))
+    return cand, n2
+
+
+def mapr_ambiguous(I: torch.Tensor, S: Setup, band: float) -> torch.Tensor:
+    """Cell-directions whose MAPR plane choice a lower precision may take
+    differently: a candidate whose gradient differs from the flattest one's
+    (by more than 1e-6 of the largest gradient of the direction) has a
+    squared norm within a relative ``band`` of the smallest.  bool [.., N]."""
+    cand, n2 = mapr_candidates(I, S)
+    nmin = n2.min(-1, keepdim=True).values
+    near = n2 <= nmin * (1.0 + band)
+    k = torch.argmin(n2, -1, keepdim=True)
+    best = torch.gather(cand, -2, k[..., None].expand(k.shape + (2,)))
+    gmax = torch.sqrt(torch.where(torch.isfinite(n2), n2, torch.zeros_like(n2)).max(-1).values)
+    differs = ((cand - best).abs().amax(-1) > 1e-6 * gmax[..., None])
+    return (near & differs).any(-1)
+
+
 def angular_divergence(I: torch.Tensor, S: Setup) -> torch.Tensor:
     """sum over the edges of each angular cell of sigma F_e: [.., N].
     Upwind value: the cell value (DC) or, with angular PLM on the
@@ -276,17 +304,13 @@ def angular_divergence(I: torch.Tensor, S: Setup) -> torch.Tensor:
     Ihi = I[..., hi]
     if getattr(S.prob, "ang_recon", 0) == 2:
         # MAPR: per cell-direction the flattest of the candidate planes
-        nbr, nxt, inv, valid, d_lo, d_hi = S.mapr
-        dI = I[..., nbr] - I[..., None]                          # [.., N, 6]
-        dJ = torch.gather(dI, -1, nxt.expand(dI.shape))
-        cand = torch.einsum("nikl,...nil->...nik", inv, torch.stack([dI, dJ], -1))
-        n2 = torch.where(valid, (cand * cand).sum(-1), torch.full_like(dI, math.inf))
+        _, _, _, _, d_lo, d_hi = S.mapr
+        cand, n2 = mapr_candidates(I, S)
         # the first candidate (in the grid's order) within a relative
         # tolerance of the flattest: ties between equally flat planes, which
         # the grid's symmetry produces, are broken by position, not by
-        # rounding (tolerance: the precision of the path being checked)
-        tie = getattr(S.prob, "mapr_tie", MAPR_TIE)
-        near = n2 <= n2.min(-1, keepdim=True).values * (1.0 + tie)
+        # rounding
+        near = n2 <= n2.min(-1, keepdim=True).values * (1.0 + MAPR_TIE)
         k = torch.argmax(near.to(torch.int8), -1, keepdim=True)
         grad = torch.gather(cand, -2, k[..., None].expand(k.shape + (2,))).squeeze(-2)
         Ilo = Ilo + (grad[..., lo, :] * d_lo).sum(-1)

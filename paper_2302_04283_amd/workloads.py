@@ -201,9 +201,6 @@ class Problem:
     # (latitude-longitude only)
     latlong: Optional[tuple] = None
     ang_recon: int = 0
-    # MAPR: relative tolerance under which two candidate planes count as
-    # equally flat (1e-10 for FP64 intensities, 1e-5 for FP32)
-    mapr_tie: float = 1e-10
     # optional fixed-intensity beam cells
     beam_mask: Optional[np.ndarray] = None   # [n2][n1][n0] bool
     beam_I: float = 0.0

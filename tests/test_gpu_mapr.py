@@ -2,15 +2,25 @@
 C ABI against the oracle (general kernel: Kerr-Schild and flat spherical
 coordinates, geodesic levels 2, 3 and 6).
 
-Tolerances as for DC: FP64 intensities 1e-12, gas temperature 1e-13; FP32
-intensities 1e-5, gas temperature 2e-7.  MAPR picks the flattest candidate
-plane; planes within a relative tolerance of the flattest count as equally
-flat and the first in the neighbour order wins (the grid's symmetry makes
-exact ties, e.g. a direction whose neighbours are all masked).  The kernel's
-tolerance is 1e-10 in FP64 and 1e-5 in FP32, and the oracle is run with the
-same one.  A gap between two candidates right at the tolerance could still be
-decided differently by the two precisions, so the FP32 cases are kept to a
-few thousand cell-directions.
+MAPR picks the flattest candidate plane; planes within a relative 1e-10 of
+the flattest count as equally flat and the first in the neighbour order wins
+(the grid's symmetry makes exact ties, e.g. a direction whose neighbours are
+all masked).  The FP64 kernel uses the oracle's rule, and FP64 runs are
+compared over three steps at 1e-12 (intensities) and 1e-13 (gas
+temperature).
+
+The FP32 kernel takes the same rule with a tie band of 1e-5 (its rounding
+would otherwise split exact ties), so where two candidates with different
+gradients are within about that band of each other it may take the other
+plane: several results are correct there.  The FP32 cases therefore start
+both sides from the same FP32-rounded state and run one step; the oracle
+reports the cell-directions whose choice lies within a band of 1e-4 (ten
+times the kernel's tie band plus its rounding), together with their angular
+neighbours (an edge's face value comes from its upwind direction's plane).
+Everything else is compared at the FP32 bars (1e-5 on I* and I, 2e-7 on T in
+cells without such a direction), the set-aside fraction is reported and
+bounded, and each set-aside value must equal the oracle's under either tie
+rule (strict minimum, or first within the band).
 """
 import math
 
@@ -41,28 +51,94 @@ def _problem(kind, nlev):
     return p
 
 
-@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
 @pytest.mark.parametrize("kind,nlev", [("ks", 2), ("ks", 3), ("sph", 3), ("c5", 6)])
-def test_mapr_step_matches_oracle(kind, nlev, prec):
-    if kind == "c5" and prec == rt.RT_F32:
-        pytest.skip("level 6 in FP64 only: 362 directions x 96 cells is too many near ties for FP32")
+def test_mapr_step_matches_oracle_fp64(kind, nlev):
     p = _problem(kind, nlev)
-    p.mapr_tie = 1e-10 if prec == rt.RT_F64 else 1e-5     # the kernel's tie tolerance
     S = O.setup(p)
     dt = O.max_dt(S, 0.3)
     Io, To, dTo, Jo, _ = oracle_run(p, 3, dt)
-    Ig, Tg, dTg, Jg, g = gpu_run(p, prec, 3, dt)
+    Ig, Tg, dTg, Jg, g = gpu_run(p, rt.RT_F64, 3, dt)
     assert not g.fast_path
     g.close()
     eI = rel_err(Ig, Io)
     eT = float(np.max(np.abs(Tg - To) / To))
     edT = float(np.max(np.abs(dTg - dTo)) / max(np.abs(dTo).max(), 1e-300))
-    print("[mapr] %s level %d %s e_I=%.2e e_T=%.2e e_dT0=%.2e" % (
-        kind, nlev, "fp64" if prec == rt.RT_F64 else "fp32", eI, eT, edT), flush=True)
-    if prec == rt.RT_F64:
-        assert eI <= 1e-12 and eT <= 1e-13 and edT <= 1e-12
-    else:
-        assert eI <= 1e-5 and eT <= 2e-7
+    print("[mapr] %s level %d fp64 e_I=%.2e e_T=%.2e e_dT0=%.2e" % (kind, nlev, eI, eT, edT),
+          flush=True)
+    assert eI <= 1e-12 and eT <= 1e-13 and edT <= 1e-12
+
+
+BAND = 1e-4
+
+
+def _affected(I, S):
+    """MAPR choices within BAND, and their edge neighbours: bool [.., N]."""
+    amb = O.mapr_ambiguous(I, S, BAND)
+    hits = amb.to(torch.int32)
+    # every direction sharing an edge with a flagged one (an accumulating
+    # scatter: a direction is the lo or hi end of several edges)
+    d = hits.dim() - 1
+    hits = hits.index_add(d, S.edge_lo, amb[..., S.edge_hi].to(torch.int32))
+    hits = hits.index_add(d, S.edge_hi, amb[..., S.edge_lo].to(torch.int32))
+    return hits > 0
+
+
+def _oracle_step(p, S, I, T, dt, tie):
+    """One oracle step under a given tie rule: (I*, I+, T+)."""
+    saved = O.MAPR_TIE
+    O.MAPR_TIE = tie
+    try:
+        rho, u, ka, ks = O.fluid_tensors(p)
+        Is, _ = O.transport(I, S, dt)
+        Ip, Tp, _ = O.coupling(Is, T, S, rho, u, ka, ks, dt)
+    finally:
+        O.MAPR_TIE = saved
+    return Is.numpy(), Ip.numpy(), Tp.numpy()
+
+
+@pytest.mark.parametrize("kind,nlev", [("ks", 2), ("ks", 3), ("sph", 3), ("c5", 6)])
+def test_mapr_step_matches_oracle_fp32(kind, nlev):
+    p = _problem(kind, nlev)
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    I0 = p.initial_intensity().astype(np.float32).astype(np.float64)   # shared start
+    It = torch.as_tensor(I0)
+    T0 = torch.as_tensor(p.T)
+    Isa, Ipa, Tpa = _oracle_step(p, S, It, T0, dt, O.MAPR_TIE)        # strict minimum
+    Isb, Ipb, Tpb = _oracle_step(p, S, It, T0, dt, BAND)              # first within the band
+    aff = _affected(It, S).numpy()
+    cell_ok = ~aff.any(-1)
+    # GPU: one step with the transport result I* as a second output
+    dev = torch.device("cuda", 0)
+    g = rt.Grid(p, rt.RT_F32)
+    assert not g.fast_path
+    Ia = torch.as_tensor(I0).to(dev, torch.float32)
+    Ib = torch.empty_like(Ia)
+    Istar = torch.empty_like(Ia)
+    T = torch.as_tensor(p.T).to(dev)
+    rho, u, ka, ks = (torch.as_tensor(x).to(dev) for x in
+                      (p.rho, p.u_tet, p.kappa_a, p.kappa_s))
+    g.step(Ia, Ib, T, rho, u, ka, ks, dt, I_star=Istar)
+    torch.cuda.synchronize()
+    g.close()
+    Isg = Istar.double().cpu().numpy()
+    Ipg = Ib.double().cpu().numpy()
+    Tg = T.cpu().numpy()
+    frac = float(aff.mean())
+    eIs = rel_err(Isg[~aff], Isa[~aff])
+    eIp = rel_err(Ipg[cell_ok], Ipa[cell_ok])
+    eT = float(np.max(np.abs(Tg[cell_ok] - Tpa[cell_ok]) / Tpa[cell_ok]))
+    # set-aside values: the oracle's under one of the two tie rules
+    scale = np.abs(Isa) + 1e-3 * np.abs(Isa).max()
+    alt = np.minimum(np.abs(Isg - Isa), np.abs(Isg - Isb)) / scale
+    eAlt = float(alt[aff].max()) if aff.any() else 0.0
+    print("[mapr] %s level %d fp32 one step: e_I*=%.2e e_I=%.2e e_T=%.2e; set aside %d of %d "
+          "cell-directions (%.2e), %d of %d cells; set-aside vs either rule %.2e" % (
+              kind, nlev, eIs, eIp, eT, int(aff.sum()), aff.size, frac,
+              int((~cell_ok).sum()), cell_ok.size, eAlt), flush=True)
+    assert eIs <= 1e-5 and eIp <= 1e-5 and eT <= 2e-7
+    assert frac <= 5e-3 and cell_ok.mean() >= 0.9
+    assert eAlt <= 1e-5
 
 
 def test_mapr_declines_adjoint_and_latlong():
@@ -82,27 +158,61 @@ def test_mapr_declines_adjoint_and_latlong():
         rt.Grid(p, rt.RT_F64)
 
 
+def _dilate(mask, reach):
+    """Cells within `reach` cells of a marked cell along any one axis (wrapping
+    at every boundary, which only sets aside more)."""
+    out = mask.copy()
+    for ax in range(3):
+        for r in range(1, reach + 1):
+            out |= np.roll(mask, r, ax) | np.roll(mask, -r, ax)
+    return out
+
+
 @pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
 def test_mapr_with_two_stages_tau_and_substitute(prec):
     """MAPR inside the extended kernel: two stages, the tau flux and the
-    velocity substitute together (Kerr-Schild, geodesic level 2)."""
+    velocity substitute together (Kerr-Schild, geodesic level 2).  FP64:
+    three steps.  FP32: one step from a shared FP32-rounded state; cells
+    whose plane choice (on the starting state, or on the oracle's stage-1
+    state with a wider band for its FP32 rounding) lies within the band are
+    set aside together with the cells whose stage-2 transport reads them."""
     p = _problem("ks", 2)
-    p.mapr_tie = 1e-10 if prec == rt.RT_F64 else 1e-5
     p.integrator, p.tau_coeff, p.rad_velocity = 2, 3.0, 1
     p.rho = p.rho * 1e-3
     S = O.setup(p)
     dt = O.max_dt(S, 0.3)
-    Io, To, dTo, Jo, _ = oracle_run(p, 3, dt)
-    Ig, Tg, dTg, Jg, g = gpu_run(p, prec, 3, dt)
-    g.close()
-    eI = rel_err(Ig, Io)
-    eT = float(np.max(np.abs(Tg - To) / To))
     cv = p.kb_mu_mp / (p.gamma_gas - 1.0)
     Erad = (np.asarray(p.initial_intensity()) * S.domega.numpy()).sum(-1)
     cond = max(1.0, float(np.max(Erad / (p.rho * cv * p.T))))
-    print("[mapr] combined options %s e_I=%.2e e_T=%.2e (cond %.0f)" % (
-        "fp64" if prec == rt.RT_F64 else "fp32", eI, eT, cond), flush=True)
+    if prec == rt.RT_F64:
+        Io, To, dTo, Jo, _ = oracle_run(p, 3, dt)
+        Ig, Tg, dTg, Jg, g = gpu_run(p, prec, 3, dt)
+        g.close()
+        keep = np.ones(To.shape, dtype=bool)
+        nset = 0
+    else:
+        I0 = p.initial_intensity().astype(np.float32).astype(np.float64)
+        Io, To, dTo, Jo, _ = oracle_run(p, 1, dt, I0=I0)
+        Ig, Tg, dTg, Jg, g = gpu_run(p, prec, 1, dt, I0=I0)
+        g.close()
+        # stage 1 of the two-stage step is the one-stage step (same dt)
+        p1 = W.make_problem("c3", scale=(8, 6, 4), nlev=2)
+        p1.ang_recon, p1.tau_coeff, p1.rad_velocity = 2, 3.0, 1
+        p1.rho = p1.rho * 1e-3
+        S1 = O.setup(p1)
+        I1, _, _, _ = O.run(p1, S1, I0, p1.T, dt, 1)
+        amb1 = O.mapr_ambiguous(torch.as_tensor(I0), S, BAND).numpy().any(-1)
+        amb2 = O.mapr_ambiguous(I1, S, 10 * BAND).numpy().any(-1)
+        # a stage-1 choice reaches the stage-2 transport of cells up to two
+        # away; a stage-2 choice stays in its cell
+        keep = ~(_dilate(amb1, 2) | amb2)
+        nset = int((~keep).sum())
+    eI = rel_err(Ig[keep], Io[keep])
+    eT = float(np.max(np.abs(Tg[keep] - To[keep]) / To[keep]))
+    print("[mapr] combined options %s e_I=%.2e e_T=%.2e (cond %.0f); %d of %d cells set aside" % (
+        "fp64" if prec == rt.RT_F64 else "fp32", eI, eT, cond, nset, keep.size), flush=True)
     if prec == rt.RT_F64:
         assert eI <= 1e-12 and eT <= 1e-13 * cond
     else:
+        assert keep.mean() >= 0.5
         assert eI <= 1e-5 and eT <= 2e-7 * cond
