@@ -150,6 +150,11 @@ typedef struct {
     int32_t n_zeta, n_psi;     /* n_zeta > 0: latitude-longitude grid instead of the geodesic one */
     int32_t ang_recon;         /* angular reconstruction: 0 = DC, 1 = PLM (latitude-longitude),
                                   2 = MAPR (geodesic) */
+    int32_t kernel;            /* 0 = the fastest step kernel the problem allows; 1 = always
+                                  the general kernel (a reference for the faster ones); 2 = the
+                                  column kernel wherever the problem allows it */
+    int32_t seglen;            /* cells per workgroup segment along axis 2 of the marching
+                                  kernels; 0 = chosen from the grid size */
 } rt_grid_desc;
 
 /*
@@ -178,8 +183,9 @@ int rt_latlong_angles(int32_t n_zeta, int32_t n_psi, double *nhat, double *domeg
 
 /*
  * Number of directions and of angular-grid edges, and which step kernel the
- * grid uses: 1 = the tiled fast path for spatially uniform geometry, 0 = the
- * general kernel.  Any output may be NULL.
+ * grid uses: 1 = the tiled kernel for spatially uniform geometry, 2 = the
+ * column kernel for geometry independent of axis 2 (one-stage step, DC
+ * angular fluxes), 0 = the general kernel.  Any output may be NULL.
  */
 int rt_grid_info(const rt_grid *g, int32_t *nang, int32_t *nedge, int32_t *fast_path);
 

@@ -1,0 +1,513 @@
+// Fused radiation step for geometry that does not depend on axis 2 (e.g. the
+// stationary, axisymmetric Kerr-Schild spacetime in spherical coordinates,
+// with axis 2 = phi; paper Sec. 2.1-2.2): every geometry table of a cell
+// column (i, j) -- face coefficients, q, signs, mask, angular-edge weights --
+// is the same for all of its cells along axis 2.
+//
+// Mapping (gfx950): one 64-lane wavefront marches one column segment along
+// axis 2; lane l handles directions l, l+64, ... (NCH chunks), so the
+// coupling's per-cell FP64 angle sums stay wavefront reductions.
+//   * the column's geometry is loaded once per segment into registers
+//     (q and the five face coefficients per direction, sign/mask/ghost flags
+//     packed in one word) and, with FP32 intensities, its angular-edge
+//     weights into LDS;
+//   * axis-2 neighbours come from a four-plane register queue (each plane
+//     of the column is read from HBM once per segment; the next plane is
+//     loaded while the current one is computed), and the axis-2 face flux
+//     of a plane is carried to the next plane, so the plane below is not
+//     needed;
+//   * axis-0/1 neighbour rows (two columns each way for PLM) are loaded one
+//     axis at a time, so only one axis's rows are live;
+//   * the cell's own row is staged in LDS for the angular-edge gather;
+//   * workgroups are dispatched round-robin over the 8 XCDs; the logical
+//     order gives each XCD a contiguous band of columns, so neighbour
+//     columns marching at the same time share an L2.
+// The per-direction arithmetic is the general kernel's (same expressions,
+// same order), so both give bit-identical results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "k_transport.h"
+
+namespace rt {
+namespace {
+
+constexpr int kColBlock = 256;
+// resident waves per SIMD the register allocation is held to: the column's
+// geometry and plane queue live in registers, about 25 VGPRs per direction
+// chunk in FP32 and 40 in FP64 on top of the coupling's working set
+template <typename Real, int NCH>
+constexpr int col_waves() {
+    return sizeof(Real) == 4 ? (NCH <= 1 ? 4 : (NCH <= 3 ? 3 : 2)) : (NCH <= 2 ? 3 : 2);
+}
+constexpr int kColWaves = kColBlock / kWave;
+
+__device__ __forceinline__ void col_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// flag word of one direction of a column
+constexpr unsigned kSxlP = 1u << 0, kSxlN = 1u << 1, kSxhP = 1u << 2, kSxhN = 1u << 3;
+constexpr unsigned kSylP = 1u << 4, kSylN = 1u << 5, kSyhP = 1u << 6, kSyhN = 1u << 7;
+constexpr unsigned kSzP = 1u << 8, kSzN = 1u << 9, kMsk = 1u << 10;
+constexpr int kGhostShift = 16;   // bits 16..23: neighbour slot k (x-2, x-1, x+1, x+2,
+                                  // y-2, y-1, y+1, y+2) reads zero (vacuum ghost)
+
+__device__ __forceinline__ unsigned sign_bits(int s, unsigned pos, unsigned neg) {
+    return s > 0 ? pos : (s < 0 ? neg : 0u);
+}
+
+// face value of the face between the cells of v[1] and v[2] (upwind from
+// the left: v[1] + delta/2) or of v[2] and v[3] ... written exactly as the
+// general kernel's axis_div forms them
+template <typename Real>
+__device__ __forceinline__ void axis_faces(const Real (&v)[5], bool plm, unsigned lo_p,
+                                           unsigned lo_n, unsigned hi_p, unsigned hi_n,
+                                           Real &ulo, Real &uhi) {
+    Real dlm = Real(0), dl0 = Real(0), dlp = Real(0);
+    if (plm) {
+        dlm = van_leer(v[1] - v[0], v[2] - v[1]);
+        dl0 = van_leer(v[2] - v[1], v[3] - v[2]);
+        dlp = van_leer(v[3] - v[2], v[4] - v[3]);
+    }
+    ulo = lo_p ? v[1] + Real(0.5) * dlm : (lo_n ? v[2] - Real(0.5) * dl0 : Real(0));
+    uhi = hi_p ? v[2] + Real(0.5) * dl0 : (hi_n ? v[3] - Real(0.5) * dlp : Real(0));
+}
+
+// VWLDS: the column's edge weights staged in LDS (FP32)
+template <typename Real, int NCH, bool VWLDS>
+__global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_waves<Real, NCH>()))) void k_column(
+    DevGrid G, ColumnInfo CI, const Real *__restrict__ Iin, Real *__restrict__ Iout,
+    double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
+    const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt,
+    double *__restrict__ dT0, double *__restrict__ partials, int *__restrict__ nr_partial,
+    Real *__restrict__ Istar) {
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int N = G.nang;
+    const int E = G.nedge;
+    __shared__ int s_adj[kMaxAngGeneral * kMaxNbr];
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    // per wave: the cell's row [N] and (FP32) the column's edge weights [2E]
+    Real *s_own = reinterpret_cast<Real *>(s_dyn) + (size_t)wave * CI.wave_lds;
+    Real *s_vw = s_own + CI.own_stride;
+    for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
+
+    // XCD-aware logical block: the hardware hands block b to XCD b % 8
+    const int per = gridDim.x / 8;
+    const int logical = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    const long long work = (long long)logical * kColWaves + wave;
+    const bool active = work < CI.nwork;
+    const long long pcells = (long long)G.n0 * G.n1;
+    int i = 0, j = 0, z0 = 0, z1 = 0;
+    if (active) {
+        i = (int)(work % G.n0);
+        const long long rest = work / G.n0;
+        j = (int)(rest % G.n1);
+        const int seg = (int)(rest / G.n1);
+        z0 = seg * CI.seglen;
+        z1 = min(G.n2, z0 + CI.seglen);
+    }
+    Cell x;
+    x.i = i;
+    x.j = j;
+    x.k = 0;
+    x.c = (long long)j * G.n0 + i;
+    x.gc = (G.g1 > 1 ? j : 0) * G.g0 + (G.g0 > 1 ? i : 0);
+    const Real *q = static_cast<const Real *>(G.q);
+    const Real *vw = static_cast<const Real *>(G.vw);
+    const Real ivol = static_cast<const Real *>(G.invV)[x.gc];
+    const double volD = G.volD[x.gc];
+    const double n0 = G.n0u[x.gc];
+    const bool plm = G.recon == RT_RECON_PLM;
+    const Real dtR = Real(dt);
+
+    // ------------------------------------------------ column geometry, once
+    const int fxl = face_geo(G, 0, i, x), fxh = face_geo(G, 0, i + 1, x);
+    const int fyl = face_geo(G, 1, j, x), fyh = face_geo(G, 1, j + 1, x);
+    const int fz = face_geo(G, 2, 0, x);   // every axis-2 face of the column
+    // neighbour columns along axes 0 and 1 and the faces beyond which a
+    // vacuum ghost sits (-1: the neighbour is an active or periodic cell)
+    int ncol[8], gface[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int a = k / 4;
+        const int o = (k % 4) < 2 ? (k % 4) - 2 : (k % 4) - 1;
+        const int coord = a == 0 ? i : j;
+        const int len = a == 0 ? G.n0 : G.n1;
+        int idx = coord + o;
+        gface[k] = -1;
+        if (idx < 0 || idx >= len) {
+            const int side = idx < 0 ? 0 : 1;
+            if (G.bc[a][side] == RT_BC_PERIODIC) {
+                idx = ((idx % len) + len) % len;
+            } else {
+                gface[k] = face_geo(G, a, side ? len : 0, x);
+                idx = side ? len - 1 : 0;
+            }
+        }
+        ncol[k] = a == 0 ? j * G.n0 + idx : idx * G.n0 + i;
+    }
+    Real gq[NCH], cxl[NCH], cxh[NCH], cyl[NCH], cyh[NCH], czz[NCH];
+    unsigned fl[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int n = lane + kWave * ch;
+        const int m = n < N ? n : 0;
+        const Real *C0 = static_cast<const Real *>(G.C[0]);
+        const Real *C1 = static_cast<const Real *>(G.C[1]);
+        const Real *C2 = static_cast<const Real *>(G.C[2]);
+        gq[ch] = q[(size_t)x.gc * N + m];
+        cxl[ch] = C0[(size_t)fxl * N + m];
+        cxh[ch] = C0[(size_t)fxh * N + m];
+        cyl[ch] = C1[(size_t)fyl * N + m];
+        cyh[ch] = C1[(size_t)fyh * N + m];
+        czz[ch] = C2[(size_t)fz * N + m];
+        unsigned f = sign_bits(G.sgn[0][(size_t)fxl * N + m], kSxlP, kSxlN) |
+                     sign_bits(G.sgn[0][(size_t)fxh * N + m], kSxhP, kSxhN) |
+                     sign_bits(G.sgn[1][(size_t)fyl * N + m], kSylP, kSylN) |
+                     sign_bits(G.sgn[1][(size_t)fyh * N + m], kSyhP, kSyhN) |
+                     sign_bits(G.sgn[2][(size_t)fz * N + m], kSzP, kSzN);
+        if (G.mask[(size_t)x.gc * N + m]) f |= kMsk;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (gface[k] < 0) continue;
+            // ghost beyond a lower (slots 0, 1) or upper face: the edge cell
+            // for directions leaving through it, zero for directions entering
+            const int s = G.sgn[k / 4][(size_t)gface[k] * N + m];
+            const bool out = (k % 4) < 2 ? (s < 0) : (s > 0);
+            if (!out) f |= 1u << (kGhostShift + k);
+        }
+        fl[ch] = f;
+    }
+    if (VWLDS && active) {
+        const Real *row = vw + (size_t)x.gc * E * 2;
+        for (int k = lane; k < 2 * E; k += kWave) s_vw[k] = row[k];
+    }
+    const Real *vwrow = VWLDS ? s_vw : vw + (size_t)x.gc * E * 2;
+    __syncthreads();   // s_adj, s_vw
+
+    double lum_acc = 0.0, me_acc = 0.0;
+    int nr_acc = 0;
+    if (active) {
+        // plane pz of column `col` for the lane's directions, with the axis-2
+        // boundary condition (vacuum ghosts: the edge cell for directions
+        // leaving through that face, zero otherwise)
+        auto load_row = [&](int pz, int col, Real (&dst)[NCH]) {
+            long long zz = pz;
+            unsigned need = 0;
+            if (pz < 0 || pz >= G.n2) {
+                const int side = pz < 0 ? 0 : 1;
+                if (G.bc[2][side] == RT_BC_PERIODIC) {
+                    zz = ((pz % G.n2) + G.n2) % G.n2;
+                } else {
+                    need = side ? kSzP : kSzN;
+                    zz = side ? G.n2 - 1 : 0;
+                }
+            }
+            const Real *src = Iin + (zz * pcells + col) * N;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                const Real v = src[ch < NCH - 1 ? n : min(n, N - 1)];
+                dst[ch] = (need == 0 || (fl[ch] & need)) ? v : Real(0);
+            }
+        };
+        // the four neighbour rows of axis a (0 or 1) at plane pz
+        auto load_axis = [&](int pz, int a, Real (&dst)[4][NCH]) {
+            const Real *base = Iin + (long long)pz * pcells * N;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * a + kk;
+                const bool need = plm || kk == 1 || kk == 2;
+                const Real *src = base + (long long)ncol[k] * N;
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int n = lane + kWave * ch;
+                    const Real v = need ? src[ch < NCH - 1 ? n : min(n, N - 1)] : Real(0);
+                    dst[kk][ch] = (fl[ch] & (1u << (kGhostShift + k))) ? Real(0) : v;
+                }
+            }
+        };
+        const int mycol = (int)x.c;
+        // planes z-1 .. z+2 of the column; the lower axis-2 face flux of the
+        // segment's first plane is formed here (it also needs plane z0-2)
+        Real qz[4][NCH];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) load_row(z0 - 1 + p, mycol, qz[p]);
+        Real Fz[NCH];
+        {
+            Real below[NCH];
+            load_row(z0 - 2, mycol, below);
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const Real v[5] = {Real(0), below[ch], qz[0][ch], qz[1][ch], qz[2][ch]};
+                Real ulo, uhi;
+                axis_faces(v, plm, 0u, 0u, fl[ch] & kSzP, fl[ch] & kSzN, ulo, uhi);
+                (void)ulo;
+                Fz[ch] = czz[ch] * uhi;
+            }
+        }
+        const bool lum_col = (G.lum_axis == 0 && i == (G.lum_side ? G.n0 - 1 : 0)) ||
+                             (G.lum_axis == 1 && j == (G.lum_side ? G.n1 - 1 : 0));
+
+        for (int z = z0; z < z1; ++z) {
+            const long long c = (long long)z * pcells + x.c;
+            const bool more = z + 1 < z1;
+            // the column's next plane while this one is computed
+            Real qn[NCH];
+            if (more) load_row(z + 3, mycol, qn);
+            // the cell's row into LDS for the angular gather
+            col_wave_sync();
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                if (n < N) s_own[n] = qz[1][ch];
+            }
+            col_wave_sync();
+            const bool lum_here = lum_col || (G.lum_axis == 2 && z == (G.lum_side ? G.n2 - 1 : 0));
+            // ------------------------------------------------------ transport
+            // axis by axis (one axis's neighbour rows live at a time)
+            Real dq[NCH];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) dq[ch] = Real(0);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                Real nb[4][NCH];
+                load_axis(z, a, nb);
+                const unsigned lp = a ? kSylP : kSxlP, ln = a ? kSylN : kSxlN;
+                const unsigned hp = a ? kSyhP : kSxhP, hn = a ? kSyhN : kSxhN;
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int n = lane + kWave * ch;
+                    const unsigned f = fl[ch];
+                    const Real v[5] = {nb[0][ch], nb[1][ch], qz[1][ch], nb[2][ch], nb[3][ch]};
+                    Real ulo, uhi;
+                    axis_faces(v, plm, f & lp, f & ln, f & hp, f & hn, ulo, uhi);
+                    const Real Flo = (a ? cyl[ch] : cxl[ch]) * ulo;
+                    const Real Fhi = (a ? cyh[ch] : cxh[ch]) * uhi;
+                    if (lum_here && G.lum_axis == a && n < N)
+                        lum_acc += G.lum_side ? -G.domega[n] * (double)Fhi : G.domega[n] * (double)Flo;
+                    dq[ch] += Fhi - Flo;
+                }
+            }
+            Real Is[NCH];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                const unsigned f = fl[ch];
+                const Real Ic = qz[1][ch];
+                {
+                    const Real v[5] = {Real(0), qz[0][ch], Ic, qz[2][ch], qz[3][ch]};
+                    Real ulo, uhi;
+                    axis_faces(v, plm, 0u, 0u, f & kSzP, f & kSzN, ulo, uhi);
+                    (void)ulo;
+                    const Real Flo = Fz[ch], Fhi = czz[ch] * uhi;
+                    Fz[ch] = Fhi;
+                    if (lum_here && G.lum_axis == 2 && n < N)
+                        lum_acc += G.lum_side ? -G.domega[n] * (double)Fhi : G.domega[n] * (double)Flo;
+                    dq[ch] += Fhi - Flo;
+                }
+                Is[ch] = Real(0);
+                if (n >= N) continue;
+                const Real div = G.has_edges ? angular_div_rec(s_adj, s_own, vwrow, n) : Real(0);
+                const Real qn_ = gq[ch];
+                const Real Qs = qn_ * Ic - dtR * ivol * dq[ch] - dtR * div / Real(G.domega[n]);
+                if (f & kMsk) {
+                    me_acc -= volD * G.domega[n] * (double)Qs;
+                    continue;
+                }
+                Is[ch] = Qs / qn_;
+            }
+            if (Istar) {
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int n = lane + kWave * ch;
+                    if (n < N) Istar[c * N + n] = Is[ch];
+                }
+            }
+            // ------------------------------------------------------ coupling
+            const double u1 = uvec[3 * c], u2 = uvec[3 * c + 1], u3 = uvec[3 * c + 2];
+            const double u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
+            const double rh = rho[c];
+            const double aa = kap_a[c] * rh, as = kap_s[c] * rh;
+            const double tau = (aa + as) * dt;
+            const double Tm = T[c];
+            double nbv[NCH], rrv[NCH];
+            double sf[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                const int m = n < N ? n : 0;
+                const double nbr_ = u0 - fma(u1, G.nhat[3 * m], fma(u2, G.nhat[3 * m + 1], u3 * G.nhat[3 * m + 2]));
+                const double nb2 = nbr_ * nbr_;
+                const double rr = rcp64(nb2 * fma(nbr_, tau, n0));
+                nbv[ch] = nbr_;
+                rrv[ch] = rr;
+                if (n >= N || (fl[ch] & kMsk)) continue;
+                const double dom = G.domega[n];
+                const double Iw = (double)Is[ch] * (nb2 * dom);
+                sf[0] += Iw;
+                sf[1] = fma(n0 * nb2 * rr, Iw, sf[1]);
+                sf[2] = fma(dom, nbr_ * rr, sf[2]);
+            }
+            wave_sum_quads(sf);
+            const double Em = sf[0], A1 = sf[1], A2 = sf[2] * (dt / kFourPi);
+            const double B4 = A2 * aa * G.a_rad;
+            const double B1 = rh * G.cv * (1.0 - A2 * as);
+            const double B0 = A1 - B1 * Tm - (1.0 - A2 * as) * Em;
+            int bad = 0;
+            const double Tp = quartic_root_fast(B4, B1, B0, bad, Tm);
+            const double Ep = Em - rh * G.cv * (Tp - Tm);
+            const double Tp2 = Tp * Tp;
+            const double S = aa * G.a_rad * Tp2 * Tp2 + as * Ep;
+            const double cS = S * (dt / kFourPi);
+            double sm[4] = {0.0, 0.0, 0.0, 0.0};
+            const bool beam_cell = G.beam != nullptr && G.beam[c];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lane + kWave * ch;
+                if (n >= N) continue;
+                Real out = Real(0);
+                if (!(fl[ch] & kMsk)) {
+                    const double nbr_ = nbv[ch], rr = rrv[ch];
+                    const double nbrr = nbr_ * rr;
+                    const double dn = fma(nbr_, tau, n0);
+                    const double I = (double)Is[ch];
+                    const double Ip = fma(n0 * nbr_ * nbrr, I, cS * (nbrr * rr * dn));
+                    const double dI = (Ip - I) * G.domega[n];
+                    sm[0] += dI;
+                    sm[1] = fma(dI, G.nhat[3 * n], sm[1]);
+                    sm[2] = fma(dI, G.nhat[3 * n + 1], sm[2]);
+                    sm[3] = fma(dI, G.nhat[3 * n + 2], sm[3]);
+                    out = Real(Ip);
+                }
+                if (beam_cell && n == G.beam_angle) out = Real(G.beam_I);
+                Iout[c * N + n] = out;
+            }
+            if (lane == 0) {
+                T[c] = Tp;
+                nr_acc += bad;
+            }
+            if (dT0) {
+                wave_sum_quads(sm);
+                if (lane == 0) {
+                    const double *E0 = G.E0 + 16 * x.gc;
+#pragma unroll
+                    for (int al = 0; al < 4; ++al)
+                        dT0[4 * c + al] -= n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
+                                                 E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
+                }
+            }
+            if (more) {
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    qz[0][ch] = qz[1][ch];
+                    qz[1][ch] = qz[2][ch];
+                    qz[2][ch] = qz[3][ch];
+                    qz[3][ch] = qn[ch];
+                }
+            }
+        }
+    }
+    // -------------------------------------------------------- block partials
+    __shared__ double sh_l[kColWaves], sh_m[kColWaves];
+    __shared__ int sh_n[kColWaves];
+    lum_acc = group_sum<kWave>(lum_acc);
+    me_acc = group_sum<kWave>(me_acc);
+    nr_acc = group_sum_i<kWave>(nr_acc);
+    if (lane == 0) {
+        sh_l[wave] = lum_acc;
+        sh_m[wave] = me_acc;
+        sh_n[wave] = nr_acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double l = 0.0, m = 0.0;
+        int r = 0;
+        for (int w = 0; w < kColWaves; ++w) {
+            l += sh_l[w];
+            m += sh_m[w];
+            r += sh_n[w];
+        }
+        partials[2 * blockIdx.x] = l;
+        partials[2 * blockIdx.x + 1] = m;
+        nr_partial[blockIdx.x] = r;
+    }
+}
+
+template <typename Real>
+int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                    const double *rho, const double *u, const double *ka, const double *ks,
+                    double dt, double *dT0, void *Istar, const Partials &P) {
+    const ColumnInfo &CI = g->column;
+    const DevGrid &G = g->dg;
+    constexpr bool VWLDS = sizeof(Real) == 4;
+    const size_t lds = (size_t)kColWaves * CI.wave_lds * sizeof(Real);
+    const int nch = (G.nang + kWave - 1) / kWave;
+#define RT_COL(NC)                                                                             \
+    case NC:                                                                                   \
+        hipLaunchKernelGGL((k_column<Real, NC, VWLDS>), dim3(CI.grid), dim3(kColBlock), lds, s, \
+                           G, CI, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, \
+                           rho, u, ka, ks, dt, dT0, P.sums, P.noroot,                          \
+                           static_cast<Real *>(Istar));                                        \
+        break;
+    switch (nch) {
+        RT_COL(1)
+        RT_COL(2)
+        RT_COL(3)
+        RT_COL(4)
+        RT_COL(5)
+        RT_COL(6)
+        RT_COL(7)
+        RT_COL(8)
+        default:
+            return RT_EINVAL;
+    }
+#undef RT_COL
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
+}
+
+}  // namespace
+
+// Segments of the column march: enough workgroups to fill the chip several
+// times over (about 32 wavefronts per CU), at least 4 planes per segment.
+bool column_config(rt_grid *g, int seglen_hint, bool force) {
+    ColumnInfo &CI = g->column;
+    const DevGrid &G = g->dg;
+    const long long cols = (long long)G.n0 * G.n1;
+    long long seglen = seglen_hint > 0 ? seglen_hint
+                                       : std::max<long long>(4, (G.n2 * cols + 8191) / 8192);
+    seglen = std::min<long long>(seglen, G.n2);
+    const long long nseg = (G.n2 + seglen - 1) / seglen;
+    const long long nwork = cols * nseg;
+    const long long blocks = (nwork + kColWaves - 1) / kColWaves;
+    if (blocks >= (1LL << 30)) return false;
+    CI.seglen = (int)seglen;
+    CI.nseg = (int)nseg;
+    CI.nwork = nwork;
+    CI.grid = (int)((blocks + 7) / 8 * 8);
+    const int real = g->precision == RT_F32 ? 4 : 8;
+    // direction chunks whose registers fit without spilling (col_waves); in
+    // FP64 from three chunks on the general kernel, at more resident waves,
+    // is faster (128 x 64 x 128 x 162 Kerr-Schild: 7.4 against 9.5 ms)
+    const int nch = (G.nang + kWave - 1) / kWave;
+    if (nch > (real == 4 ? 6 : (force ? 4 : 2))) return false;
+    CI.own_stride = (G.nang + 3) / 4 * 4;
+    CI.wave_lds = CI.own_stride + (real == 4 ? 2 * G.nedge : 0);
+    // within the default dynamic LDS limit (no attribute call needed)
+    return (size_t)kColWaves * CI.wave_lds * real <= 64 * 1024;
+}
+
+int launch_column(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                  const double *rho, const double *u, const double *ka, const double *ks,
+                  double dt, double *dT0, void *Istar, const Partials &P) {
+    if (g->precision == RT_F32)
+        return launch_column_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+    return launch_column_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+}
+
+}  // namespace rt

@@ -21,7 +21,6 @@
 //     halo rows hit its own L2.
 #include <hip/hip_runtime.h>
 
-#include <cstdlib>
 #include <type_traits>
 
 #include "k_common.h"
@@ -581,8 +580,6 @@ bool march_config(int precision, int nang, int &sw, int &nc) {
     // instantiated (lane-group width, directions per lane) pairs
     static const int f32[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 4}, {32, 6}, {32, 8}};
     static const int f64[][2] = {{16, 1}, {16, 3}, {16, 6}, {32, 3}, {32, 4}, {32, 6}};
-    int want = 0;
-    if (const char *e = std::getenv("RT_MARCH_SW")) want = std::atoi(e);
     const int (*tab)[2] = precision == RT_F32 ? f32 : f64;
     const int ntab = precision == RT_F32 ? 7 : 6;
     // smallest group width whose directions-per-lane fits the register
@@ -590,9 +587,8 @@ bool march_config(int precision, int nang, int &sw, int &nc) {
     // the kernel lets only the last chunk of a lane run past nang
     const int budget = 6;
     for (int w : {16, 32}) {
-        if (want && w != want) continue;
         const int need = (nang + w - 1) / w;
-        if (!want && need > budget) continue;
+        if (need > budget) continue;
         for (int i = 0; i < ntab; ++i)
             if (tab[i][0] == w && tab[i][1] == need) {
                 sw = w;

@@ -533,7 +533,9 @@ int step_blocks(const rt_grid *g) {
 }
 
 int step_partial_blocks(const rt_grid *g) {
-    return g->march.enabled ? g->march.grid : step_blocks(g);
+    if (g->march.enabled) return g->march.grid;
+    if (g->column.enabled) return g->column.grid;
+    return step_blocks(g);
 }
 
 int scratch_address(void **ptr, size_t *bytes) {
@@ -566,6 +568,11 @@ int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *
         int rc = launch_march(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
         if (rc != RT_OK) return rc;
         return launch_finalize(g, s, g->march.grid, dt, lum, P);
+    }
+    if (g->column.enabled) {
+        int rc = launch_column(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        if (rc != RT_OK) return rc;
+        return launch_finalize(g, s, g->column.grid, dt, lum, P);
     }
     if (g->integrator == 2) {
         if (g->precision == RT_F32)

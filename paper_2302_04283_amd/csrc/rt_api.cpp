@@ -1,7 +1,6 @@
 // C ABI of the radiation step: validation, table upload, scratch, dispatch.
 #include <algorithm>
 #include <cmath>
-#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <limits>
@@ -125,6 +124,9 @@ int check_desc(const rt_grid_desc *d) {
     if (!(d->tau_coeff >= 0.0) || !std::isfinite(d->tau_coeff))
         return fail(RT_EINVAL, "tau_coeff must be finite and >= 0");
     if (d->rad_velocity < 0 || d->rad_velocity > 1) return fail(RT_EINVAL, "rad_velocity must be 0 or 1");
+    if (d->kernel < 0 || d->kernel > 2)
+        return fail(RT_EINVAL, "kernel must be 0 (fastest), 1 (general) or 2 (column where allowed)");
+    if (d->seglen < 0) return fail(RT_EINVAL, "seglen must be >= 0");
     return RT_OK;
 }
 
@@ -261,8 +263,7 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
             M.enabled = 0;
             M.any_mask = 0;
             int sw = 0, nc = 0;
-            const char *env = std::getenv("RT_MARCH");
-            const bool allow = !(env && env[0] == '0');
+            const bool allow = d->kernel != 1;
             const bool cfg = rt::march_config(d->precision, N, sw, nc);
             const size_t lds = cfg ? rt::march_lds_bytes(d->precision, N, sw * nc) : 0;
             if (allow && cfg && G == 1 && !t.has_edges &&
@@ -301,10 +302,10 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
                 M.pstride = rt::march_pstride(d->precision, sw * nc);
                 M.ntx = d->n[0] / rt::kTX;
                 const long long ntiles = (long long)(d->n[0] / rt::kTX) * (d->n[1] / rt::kTY);
-                long long target = 2048;
-                if (const char *w = std::getenv("RT_MARCH_WG")) target = std::max(1LL, std::atoll(w));
-                long long seglen = std::max<long long>(4, (d->n[2] * ntiles + target - 1) / target);
-                if (const char *sl = std::getenv("RT_MARCH_SEGLEN")) seglen = std::max(1LL, std::atoll(sl));
+                const long long target = 2048;
+                long long seglen = d->seglen > 0
+                                       ? d->seglen
+                                       : std::max<long long>(4, (d->n[2] * ntiles + target - 1) / target);
                 seglen = std::min<long long>(seglen, d->n[2]);
                 M.seglen = (int)seglen;
                 M.nseg = (int)((d->n[2] + seglen - 1) / seglen);
@@ -316,6 +317,13 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
                 }
             }
         }
+        // column march for geometry independent of axis 2 (one-stage step,
+        // DC angular fluxes)
+        g->column.enabled = 0;
+        if (!g->march.enabled && d->kernel != 1 && d->geo_extent[2] == 1 && g->integrator == 1 &&
+            !(d->tau_coeff > 0.0) && !d->rad_velocity && d->ang_recon == 0 &&
+            (N + rt::kWave - 1) / rt::kWave <= rt::kMaxChunks)
+            g->column.enabled = rt::column_config(g, d->seglen, d->kernel == 2) ? 1 : 0;
         // this device's static scratch for rt_step_noalloc (looked up once per
         // device, with the device current); a failed lookup leaves it unset and
         // only that entry point reports it
@@ -327,7 +335,8 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
                 g->scratch_bytes = sb;
             }
         }
-        g->max_blocks = std::max(rt::step_blocks(g), g->march.enabled ? g->march.grid : 0);
+        g->max_blocks = std::max({rt::step_blocks(g), g->march.enabled ? g->march.grid : 0,
+                                  g->column.enabled ? g->column.grid : 0});
         g->partials = up.zeros<double>((size_t)g->max_blocks * 2);
         g->noroot_partial = up.zeros<int>((size_t)g->max_blocks);
         g->ledger = up.zeros<double>(1);
@@ -391,7 +400,7 @@ int rt_grid_info(const rt_grid *g, int32_t *nang, int32_t *nedge, int32_t *fast_
     if (!g) return fail(RT_EINVAL, "grid is NULL");
     if (nang) *nang = g->ang.nang;
     if (nedge) *nedge = g->ang.nedge;
-    if (fast_path) *fast_path = g->march.enabled;
+    if (fast_path) *fast_path = g->march.enabled ? 1 : (g->column.enabled ? 2 : 0);
     return RT_OK;
 }
 

@@ -122,6 +122,15 @@ struct MarchInfo {
     double vol;
 };
 
+// Column march for geometry independent of axis 2 (k_column.hip).
+struct ColumnInfo {
+    int enabled;
+    int seglen, nseg, grid;
+    long long nwork;              // column segments (one wavefront each)
+    int own_stride;               // LDS entries of a wave's own row
+    int wave_lds;                 // LDS entries per wave (own row + FP32 edge weights)
+};
+
 }  // namespace rt
 
 struct rt_grid {
@@ -130,6 +139,7 @@ struct rt_grid {
     rt::Geodesic ang;
     rt::DevGrid dg{};
     rt::MarchInfo march{};
+    rt::ColumnInfo column{};
     std::vector<double> dx[3];    // coordinate widths (for rt_max_dt)
     std::vector<double> host_n0u; // [G]
     std::vector<double> host_na;  // [G][nang][3] n^a at centres (for rt_max_dt)
@@ -180,6 +190,11 @@ int launch_adjoint(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin
                    const void *Istar);
 int launch_adj_march(rt_grid *g, hipStream_t s, const void *Iin, const void *psi, double dt,
                      double lum_weight, void *lamI0);
+// k_column.hip
+bool column_config(rt_grid *g, int seglen_hint, bool force);
+int launch_column(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                  const double *rho, const double *u, const double *ka, const double *ks,
+                  double dt, double *dT0, void *Istar, const Partials &P);
 // k_gas.hip
 int launch_gas_update(rt_grid *g, hipStream_t s, const double *dT0, const double *Tpre,
                       double *rho, double *u, double *T, int32_t *status);

@@ -54,6 +54,8 @@ class RtGridDesc(C.Structure):
         ("n_zeta", C.c_int32),
         ("n_psi", C.c_int32),
         ("ang_recon", C.c_int32),
+        ("kernel", C.c_int32),
+        ("seglen", C.c_int32),
     ]
 
 
@@ -176,6 +178,8 @@ class Grid:
         if ll is not None:
             d.n_zeta, d.n_psi = int(ll[0]), int(ll[1])
         d.ang_recon = int(getattr(prob, "ang_recon", 0))
+        d.kernel = int(getattr(prob, "kernel", 0))
+        d.seglen = int(getattr(prob, "seglen", 0))
         d.vol = _ptr(arr(prob.vol))
         d.gcov_c = _ptr(arr(prob.gcov_c))
         d.dgcov_c = _ptr(arr(prob.dgcov_c))
@@ -199,7 +203,8 @@ class Grid:
         _check(lib.rt_grid_info(h, C.byref(na), C.byref(ne), C.byref(fp)))
         self.nang = na.value
         self.nedge = ne.value
-        self.fast_path = bool(fp.value)
+        self.path = int(fp.value)             # 0 general, 1 tiled, 2 column
+        self.fast_path = self.path == 1
 
     # -------------------------------------------------------------- queries
     def angles(self):

@@ -201,6 +201,11 @@ class Problem:
     # (latitude-longitude only)
     latlong: Optional[tuple] = None
     ang_recon: int = 0
+    # step kernel: 0 = the fastest one the problem allows, 1 = the general
+    # kernel, 2 = the column kernel wherever allowed; cells per workgroup
+    # segment along axis 2 (0 = automatic)
+    kernel: int = 0
+    seglen: int = 0
     # optional fixed-intensity beam cells
     beam_mask: Optional[np.ndarray] = None   # [n2][n1][n0] bool
     beam_I: float = 0.0

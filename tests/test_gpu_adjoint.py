@@ -268,18 +268,18 @@ def test_tiled_adjoint_fp32_arithmetic(bc, lum_axis, lum_side):
 
 @pytest.mark.parametrize("nlev,shape,seglen", [(4, (8, 4, 7), "3"), (2, (4, 8, 5), "2"),
                                                (1, (4, 4, 3), "1"), (3, (4, 4, 6), "4")])
-def test_tiled_adjoint_matches_general_adjoint(monkeypatch, nlev, shape, seglen):
+def test_tiled_adjoint_matches_general_adjoint(nlev, shape, seglen):
     """Tiled and general adjoint on the same inputs (FP64): direction chunks
     (162 directions span two chunks of 96, 92 one padded chunk), ragged
     segments along axis 2."""
     p = W.make_problem("c2", scale=shape, nlev=nlev)
     dt = O.max_dt(O.setup(p), 0.3)
-    monkeypatch.setenv("RT_MARCH_SEGLEN", seglen)
+    p.seglen = int(seglen)
     g = rt.Grid(p, rt.RT_F64)
     assert g.fast_path
     g.close()
     a = _gpu_grads(p, rt.RT_F64, 3, dt, 3)
-    monkeypatch.setenv("RT_MARCH", "0")
+    p.kernel = 1
     b = _gpu_grads(p, rt.RT_F64, 3, dt, 3)
     errs = {k: _max_rel(a[k], b[k]) for k in ("kappa_a", "kappa_s", "T0", "I0")}
     print("[adjoint] tiled vs general lev%d %s seglen %s %s" % (

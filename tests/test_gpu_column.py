@@ -1,0 +1,112 @@
+"""The column kernel (geometry independent of axis 2: Kerr-Schild in
+spherical coordinates, and uniform grids the tiled kernel does not take)
+against the general kernel and the oracle.
+
+Both kernels evaluate every face value, flux, angular flux and the coupling
+with the same expressions in the same order, so intensities, temperatures,
+the four-momentum bookkeeping and I* agree bit for bit; the luminosity and
+the masked-energy ledger are block sums grouped differently (1e-13).
+"""
+import numpy as np
+import pytest
+import torch
+
+from harness import gpu_run, oracle_run, rel_err
+from oracle import step as O
+from paper_2302_04283_amd import rt
+from paper_2302_04283_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(p, prec, steps, dt, kernel):
+    p.kernel = kernel
+    dev = torch.device("cuda", 0)
+    g = rt.Grid(p, prec, 0)
+    path = g.path
+    Ia = torch.as_tensor(p.initial_intensity()).to(dev, g.real_dtype())
+    Ib = torch.empty_like(Ia)
+    Is = torch.empty_like(Ia)
+    T = torch.as_tensor(p.T).to(dev)
+    rho, u, ka, ks = (torch.as_tensor(x).to(dev) for x in (p.rho, p.u_tet, p.kappa_a, p.kappa_s))
+    dT0 = torch.zeros(T.shape + (4,), dtype=torch.float64, device=dev)
+    lum = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(steps):
+        g.step(Ia, Ib, T, rho, u, ka, ks, dt, dT0, lum, I_star=Is)
+        Ia, Ib = Ib, Ia
+    torch.cuda.synchronize()
+    st = g.stats()
+    g.close()
+    p.kernel = 0
+    return Ia.cpu(), Is.cpu(), T.cpu(), dT0.cpu(), float(lum[0]), st, path
+
+
+def _cases():
+    c3 = W.make_problem("c3", scale=(16, 12, 8))
+    c3_dc = W.make_problem("c3", scale=(12, 8, 6))
+    c3_dc.recon = W.RECON_DC
+    c4 = W.make_problem("c4", scale=(10, 6, 9))
+    c5 = W.make_problem("c5", scale=(6, 4, 8))
+    # axis 2 with outflow/vacuum ends (ghosts along the march axis)
+    ks_out = W.make_custom("ks_sph", (8, 6, 7), [(2.0, 6.0), (1.0, 2.0), (0.0, 0.7)], 3,
+                           [(1, 1), (1, 1), (1, 1)], M=1.0, a=0.9)
+    ks_out.kappa_a[:] = 0.5
+    ks_out.T[:] = 1.0 + 0.2 * np.arange(ks_out.T.size).reshape(ks_out.T.shape) / ks_out.T.size
+    ks_out.lum_axis, ks_out.lum_side = 2, 0
+    # a uniform grid the tiled kernel does not take (n0 not a multiple of 4), with the beam
+    mink = W.make_problem("c2", scale=(6, 5, 7))
+    return [("c3", c3), ("c3-dc", c3_dc), ("c4", c4), ("c5", c5), ("ks-outflow-z", ks_out),
+            ("mink-beam", mink)]
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("name,prob", _cases(), ids=[c[0] for c in _cases()])
+def test_column_kernel_equals_general_kernel(name, prob, prec):
+    p = prob
+    g = rt.Grid(p, prec)
+    dt = g.max_dt(p.cfl)
+    auto = g.path
+    g.close()
+    nch = (p.nang + 63) // 64
+    # the automatic choice: the column kernel in FP32 and up to two FP64 chunks
+    assert auto == (2 if (prec == rt.RT_F32 or nch <= 2) else 0), (name, auto)
+    if prec == rt.RT_F64 and nch > 4:
+        pytest.skip("FP64 with %d direction chunks: the column kernel would spill" % nch)
+    print("[column] %s %s n=%s nang=%d" % (name, "fp64" if prec == rt.RT_F64 else "fp32",
+                                           p.n, p.nang), flush=True)
+    a = _run(p, prec, 3, dt, 2)
+    b = _run(p, prec, 3, dt, 1)
+    assert a[6] == 2 and b[6] == 0
+    for x, y, what in zip(a[:4], b[:4], ("I", "I*", "T", "dT0")):
+        assert torch.equal(x, y), what
+    assert abs(a[4] - b[4]) <= 1e-13 * max(abs(b[4]), 1e-300)
+    assert a[5]["no_root"] == b[5]["no_root"]
+    assert abs(a[5]["masked_energy"] - b[5]["masked_energy"]) <= \
+        1e-13 * max(abs(b[5]["masked_energy"]), 1e-300)
+
+
+def _forced(p, prec):
+    p.kernel = 2
+    g = rt.Grid(p, prec)
+    p.kernel = 0
+    return g
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+def test_column_kernel_matches_oracle_kerr_schild(prec):
+    p = W.make_problem("c3", scale=(16, 12, 8))
+    S = O.setup(p)
+    dt = O.max_dt(S, 0.3)
+    Io, To, dTo, Jo, _ = oracle_run(p, 4, dt)
+    Ig, Tg, dTg, Jg, g = gpu_run(p, prec, 4, dt, grid=_forced(p, prec))
+    assert g.path == 2
+    g.close()
+    eI = rel_err(Ig, Io)
+    eT = float(np.max(np.abs(Tg - To) / To))
+    eJ = abs(Jg - Jo) / abs(Jo)
+    print("[column] c3 16x12x8 vs oracle %s e_I=%.2e e_T=%.2e e_J=%.2e" % (
+        "fp64" if prec == rt.RT_F64 else "fp32", eI, eT, eJ), flush=True)
+    if prec == rt.RT_F64:
+        assert eI <= 1e-12 and eT <= 1e-13 and eJ <= 1e-12
+    else:
+        assert eI <= 1e-5 and eT <= 2e-7 and eJ <= 1e-5

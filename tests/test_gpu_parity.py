@@ -259,9 +259,9 @@ def test_fast_path_outflow_vacuum_boundaries(prec):
         assert r["eJ"] <= (F64_AUX if prec == rt.RT_F64 else 1e-5)
 
 
-def test_general_kernel_forced_matches_oracle(monkeypatch):
-    monkeypatch.setenv("RT_MARCH", "0")
+def test_general_kernel_forced_matches_oracle():
     p = W.make_problem("c2", scale=(8, 8, 8))
+    p.kernel = 1
     g = rt.Grid(p, rt.RT_F64)
     assert not g.fast_path
     g.close()

@@ -12,9 +12,9 @@ quartic is well conditioned in its coefficients (|B0| / (T P'(T)) <= 1).
 With radiation present, B0 carries the difference A1 - E-, which cancels
 when the optical depth is small; that case is covered by the end-to-end
 parity tests at their tolerances.  The no-root and overflow cases share one
-radiation field across the grid, so the transport is exactly zero.  Both
-the tiled kernel (n0, n1 multiples of 4) and the general kernel run every
-case, in FP64.
+radiation field across the grid, so the transport is exactly zero.  The
+tiled kernel (n0, n1 multiples of 4), the column kernel and the general
+kernel run every case, in FP64.
 """
 import math
 
@@ -36,7 +36,7 @@ def _grid(n):
                          [(W.BC_PERIODIC, W.BC_PERIODIC)] * 3)
 
 
-def _run_both(p, I_dir, dt):
+def _run_both(p, I_dir, dt, kernel):
     """One step of the same problem on both sides: (T_gpu, T_ora, no-root
     counts, fast_path).  I_dir: intensity per direction, the same in every cell."""
     S = O.setup(p)
@@ -47,6 +47,7 @@ def _run_both(p, I_dir, dt):
     assert float((Is - torch.as_tensor(I0)).abs().max()) == 0.0     # no transport
     _, To, _ = O.coupling(Is, torch.as_tensor(p.T), S, rho, u, ka, ks, dt, stats)
     dev = torch.device("cuda", 0)
+    p.kernel = kernel
     g = rt.Grid(p, rt.RT_F64)
     Ia = torch.as_tensor(I0).to(dev)
     Ib = torch.empty_like(Ia)
@@ -55,13 +56,18 @@ def _run_both(p, I_dir, dt):
     g.step(Ia, Ib, T, f[0], f[1], f[2], f[3], dt)
     torch.cuda.synchronize()
     nr = g.stats()["no_root"]
-    fast = g.fast_path
+    path = g.path
     g.close()
-    return T.cpu().numpy(), To.numpy(), nr, stats.get("no_root", 0), fast
+    return T.cpu().numpy(), To.numpy(), nr, stats.get("no_root", 0), path
 
 
-@pytest.mark.parametrize("n", [(8, 8, 4), (6, 6, 4)])
-def test_quartic_stiffness_sweep(n):
+# (grid, kernel choice, kernel that runs): tiled, column, general
+PATHS = [((8, 8, 4), 0, 1), ((6, 6, 4), 0, 2), ((6, 6, 4), 1, 0)]
+NAMES = {0: "general", 1: "tiled", 2: "column"}
+
+
+@pytest.mark.parametrize("n,kernel,path", PATHS)
+def test_quartic_stiffness_sweep(n, kernel, path):
     p = _grid(n)
     dt = 0.01
     rng = np.random.default_rng(17)
@@ -73,14 +79,14 @@ def test_quartic_stiffness_sweep(n):
     p.kappa_a.reshape(-1)[:8] = 0.0               # B4 = 0: T unchanged
     p.T = 10.0 ** rng.uniform(-2, 2, shp)
     I = np.zeros(p.nang)                          # empty radiation field
-    Tg, To, nr_g, nr_o, fast = _run_both(p, I, dt)
-    assert fast == (n[0] % 4 == 0)
+    Tg, To, nr_g, nr_o, got = _run_both(p, I, dt, kernel)
+    assert got == path
     cv = p.kb_mu_mp / (p.gamma_gas - 1.0)
     ratio = (tau / (1 + tau)) * p.a_rad / (rho * cv)
     assert ratio.min() < 1e-10 and ratio.max() > 1e10   # the span of B4/B1
     rel = np.abs(Tg - To) / To
     print("[quartic] %s %s: max |dT|/T = %.1f ulp, no-root %d / %d" % (
-        n, "tiled" if fast else "general", rel.max() / ULP, nr_g, nr_o), flush=True)
+        n, NAMES[path], rel.max() / ULP, nr_g, nr_o), flush=True)
     assert nr_g == nr_o == 0
     assert rel.max() <= 8 * ULP
     # no absorption: B4 = 0, the linear root -B0/B1 = T- up to the rounding of B1 T- / B1
@@ -88,8 +94,8 @@ def test_quartic_stiffness_sweep(n):
     assert np.abs(Tg.reshape(-1)[flat] / p.T.reshape(-1)[flat] - 1.0).max() <= 2 * ULP
 
 
-@pytest.mark.parametrize("n", [(8, 8, 4), (6, 6, 4)])
-def test_quartic_no_root_and_overflow_take_the_floor(n):
+@pytest.mark.parametrize("n,kernel,path", PATHS)
+def test_quartic_no_root_and_overflow_take_the_floor(n, kernel, path):
     # scattering only, fluid moving at 0.6 c along x^1; radiation beamed
     # along the motion (exp(5 n^1): the coupling asks more energy of the gas
     # than it holds, B0 >= 0) or against it (exp(-2 n^1): the gas gains
@@ -107,7 +113,8 @@ def test_quartic_no_root_and_overflow_take_the_floor(n):
         rho.reshape(-1)[5] = 1e-300
         p.rho = rho
         p.kappa_s = 3.0 / (dt * rho)
-        Tg, To, nr_g, nr_o, fast = _run_both(p, I, dt)
+        Tg, To, nr_g, nr_o, got = _run_both(p, I, dt, kernel)
+        assert got == path
         out[beam] = (Tg, To, nr_g, nr_o)
         floor_g = Tg.reshape(-1) == 1e-12
         floor_o = To.reshape(-1) == 1e-12

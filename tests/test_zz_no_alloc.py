@@ -37,7 +37,7 @@ def _one_step(prob, precision, noalloc, dt):
     return res
 
 
-@pytest.mark.parametrize("case", ["tiled_fp32", "general_fp64", "two_stage_fp32"])
+@pytest.mark.parametrize("case", ["tiled_fp32", "general_fp64", "two_stage_fp32", "column_fp32"])
 def test_noalloc_step_matches_rt_step_on_two_calls(case):
     if case == "tiled_fp32":
         big, small, prec = (W.make_problem("c2", scale=(16, 12, 10)),
@@ -45,10 +45,13 @@ def test_noalloc_step_matches_rt_step_on_two_calls(case):
     elif case == "general_fp64":
         big, small, prec = (W.make_problem("c3", scale=(16, 12, 8)),
                             W.make_problem("c3", scale=(8, 6, 4)), rt.RT_F64)
-    else:
+    elif case == "two_stage_fp32":
         big, small, prec = (W.make_problem("c2", scale=(16, 12, 10)),
                             W.make_problem("c2", scale=(8, 8, 6)), rt.RT_F32)
         big.integrator = small.integrator = 2
+    else:
+        big, small, prec = (W.make_problem("c3", scale=(16, 12, 8)),
+                            W.make_problem("c3", scale=(8, 6, 4)), rt.RT_F32)
     for prob in (big, small):              # the second call has the smaller input
         g = rt.Grid(prob, prec, 0)
         dt = g.max_dt(prob.cfl)
@@ -68,9 +71,10 @@ def test_noalloc_rejects_a_grid_beyond_the_scratch():
     n = (242, 242, 242)
     p = W.make_custom("minkowski_cart", n, [(0.0, 1.0)] * 3, 1,
                       [(W.BC_PERIODIC, W.BC_PERIODIC)] * 3)
+    p.kernel = 1
     dev = torch.device("cuda", 0)
     g = rt.Grid(p, rt.RT_F32, 0)
-    assert not g.fast_path
+    assert g.path == 0
     I = torch.empty((n[2], n[1], n[0], p.nang), dtype=torch.float32, device=dev)
     out = torch.empty_like(I)
     T, rho, ka, ks = (torch.empty((n[2], n[1], n[0]), dtype=torch.float64, device=dev)
