@@ -16,8 +16,13 @@
 //     loaded while the current one is computed), and the axis-2 face flux
 //     of a plane is carried to the next plane, so the plane below is not
 //     needed;
-//   * axis-0/1 neighbour rows (two columns each way for PLM) are loaded one
-//     axis at a time, so only one axis's rows are live;
+//   * axis-0/1 neighbour rows (two columns each way for PLM): with FP32
+//     intensities and up to three direction chunks the next plane's rows go
+//     straight from HBM/L2 into a per-wave LDS buffer (global_load_lds) as
+//     soon as the current plane's transport has read them, so their latency
+//     hides behind the angular fluxes and the coupling without holding
+//     registers; otherwise they are loaded into registers one axis at a
+//     time;
 //   * the cell's own row is staged in LDS for the angular-edge gather;
 //   * workgroups are dispatched round-robin over the 8 XCDs; the logical
 //     order gives each XCD a contiguous band of columns, so neighbour
@@ -34,6 +39,7 @@ namespace rt {
 namespace {
 
 constexpr int kColBlock = 256;
+constexpr int kColMaxAng = 6 * kWave;   // largest direction count of the column kernel
 // resident waves per SIMD the register allocation is held to: the column's
 // geometry and plane queue live in registers, about 25 VGPRs per direction
 // chunk in FP32 and 40 in FP64 on top of the coupling's working set
@@ -60,25 +66,27 @@ __device__ __forceinline__ unsigned sign_bits(int s, unsigned pos, unsigned neg)
     return s > 0 ? pos : (s < 0 ? neg : 0u);
 }
 
-// face value of the face between the cells of v[1] and v[2] (upwind from
-// the left: v[1] + delta/2) or of v[2] and v[3] ... written exactly as the
-// general kernel's axis_div forms them
+// upwind values of the lower face (between the cells of v[1] and v[2]) and
+// the upper face (v[2], v[3]) of the cell v[2]: from the left cell its
+// value plus half its van Leer slope, from the right cell its value minus
+// half of it; written exactly as the general kernel's axis_div forms them
 template <typename Real>
 __device__ __forceinline__ void axis_faces(const Real (&v)[5], bool plm, unsigned lo_p,
                                            unsigned lo_n, unsigned hi_p, unsigned hi_n,
                                            Real &ulo, Real &uhi) {
-    Real dlm = Real(0), dl0 = Real(0), dlp = Real(0);
+    Real hlm = Real(0), hl0 = Real(0), hlp = Real(0);
     if (plm) {
-        dlm = van_leer(v[1] - v[0], v[2] - v[1]);
-        dl0 = van_leer(v[2] - v[1], v[3] - v[2]);
-        dlp = van_leer(v[3] - v[2], v[4] - v[3]);
+        hlm = half_slope(v[0], v[1], v[2]);
+        hl0 = half_slope(v[1], v[2], v[3]);
+        hlp = half_slope(v[2], v[3], v[4]);
     }
-    ulo = lo_p ? v[1] + Real(0.5) * dlm : (lo_n ? v[2] - Real(0.5) * dl0 : Real(0));
-    uhi = hi_p ? v[2] + Real(0.5) * dl0 : (hi_n ? v[3] - Real(0.5) * dlp : Real(0));
+    ulo = lo_p ? v[1] + hlm : (lo_n ? v[2] - hl0 : Real(0));
+    uhi = hi_p ? v[2] + hl0 : (hi_n ? v[3] - hlp : Real(0));
 }
 
-// VWLDS: the column's edge weights staged in LDS (FP32)
-template <typename Real, int NCH, bool VWLDS>
+// VWLDS: the column's edge weights staged in LDS; DMA: axis-0/1 neighbour
+// rows prefetched into LDS (FP32)
+template <typename Real, int NCH, bool VWLDS, bool DMA>
 __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_waves<Real, NCH>()))) void k_column(
     DevGrid G, ColumnInfo CI, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
@@ -89,11 +97,13 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     const int wave = threadIdx.x / kWave;
     const int N = G.nang;
     const int E = G.nedge;
-    __shared__ int s_adj[kMaxAngGeneral * kMaxNbr];
+    __shared__ int s_adj[kColMaxAng * kMaxNbr];
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    // per wave: the cell's row [N] and (FP32) the column's edge weights [2E]
+    // per wave: the cell's row [own_stride], the column's edge weights [2E]
+    // (VWLDS), the next plane's eight neighbour rows [8][NCH][64] (DMA)
     Real *s_own = reinterpret_cast<Real *>(s_dyn) + (size_t)wave * CI.wave_lds;
     Real *s_vw = s_own + CI.own_stride;
+    Real *s_nb = s_vw + (VWLDS ? 2 * E : 0);
     for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
 
     // XCD-aware logical block: the hardware hands block b to XCD b % 8
@@ -232,7 +242,29 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 }
             }
         };
+        // the eight neighbour rows of plane pz straight into this wave's LDS
+        // buffer: each lane moves one value per (row, chunk); the last chunk's
+        // lanes past the row re-read its last entry (never used)
+        auto dma_rows = [&](int pz) {
+            if constexpr (DMA) {
+                const Real *base = Iin + (long long)pz * pcells * N;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (!plm && (k % 4 == 0 || k % 4 == 3)) continue;
+                    const Real *src = base + (long long)ncol[k] * N;
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch) {
+                        const int n = lane + kWave * ch;
+                        __builtin_amdgcn_global_load_lds(
+                            src + (ch < NCH - 1 ? n : min(n, N - 1)),
+                            (__attribute__((address_space(3))) void *)(s_nb + (k * NCH + ch) * kWave),
+                            4, 0, 0);
+                    }
+                }
+            }
+        };
         const int mycol = (int)x.c;
+        if constexpr (DMA) dma_rows(z0);
         // planes z-1 .. z+2 of the column; the lower axis-2 face flux of the
         // segment's first plane is formed here (it also needs plane z0-2)
         Real qz[4][NCH];
@@ -274,10 +306,28 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             Real dq[NCH];
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) dq[ch] = Real(0);
+            if constexpr (DMA) {
+                // this plane's neighbour rows have landed in LDS (the wave's
+                // own loads: vmcnt reaches zero)
+                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+            }
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 Real nb[4][NCH];
-                load_axis(z, a, nb);
+                if constexpr (DMA) {
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int k = 4 * a + kk;
+                        const bool need = plm || kk == 1 || kk == 2;
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch) {
+                            const Real v = need ? s_nb[(k * NCH + ch) * kWave + lane] : Real(0);
+                            nb[kk][ch] = (fl[ch] & (1u << (kGhostShift + k))) ? Real(0) : v;
+                        }
+                    }
+                } else {
+                    load_axis(z, a, nb);
+                }
                 const unsigned lp = a ? kSylP : kSxlP, ln = a ? kSylN : kSxlN;
                 const unsigned hp = a ? kSyhP : kSxhP, hn = a ? kSyhN : kSxhN;
 #pragma unroll
@@ -292,6 +342,14 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     if (lum_here && G.lum_axis == a && n < N)
                         lum_acc += G.lum_side ? -G.domega[n] * (double)Fhi : G.domega[n] * (double)Flo;
                     dq[ch] += Fhi - Flo;
+                }
+            }
+            if constexpr (DMA) {
+                if (more) {
+                    // every LDS read of this plane's rows has returned before
+                    // the next plane's rows are written over them
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+                    dma_rows(z + 1);
                 }
             }
             Real Is[NCH];
@@ -315,12 +373,12 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 if (n >= N) continue;
                 const Real div = G.has_edges ? angular_div_rec(s_adj, s_own, vwrow, n) : Real(0);
                 const Real qn_ = gq[ch];
-                const Real Qs = qn_ * Ic - dtR * ivol * dq[ch] - dtR * div / Real(G.domega[n]);
+                const Real Qs = qn_ * Ic - dtR * ivol * dq[ch] - quot(dtR * div, Real(G.domega[n]));
                 if (f & kMsk) {
                     me_acc -= volD * G.domega[n] * (double)Qs;
                     continue;
                 }
-                Is[ch] = Qs / qn_;
+                Is[ch] = quot(Qs, qn_);
             }
             if (Istar) {
 #pragma unroll
@@ -445,12 +503,16 @@ int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
                     double dt, double *dT0, void *Istar, const Partials &P) {
     const ColumnInfo &CI = g->column;
     const DevGrid &G = g->dg;
-    constexpr bool VWLDS = sizeof(Real) == 4;
     const size_t lds = (size_t)kColWaves * CI.wave_lds * sizeof(Real);
     const int nch = (G.nang + kWave - 1) / kWave;
+    // FP32: edge weights in LDS; neighbour rows by LDS DMA up to three chunks
+    // (beyond, the buffers of four waves would leave one workgroup per CU:
+    // 256 x 128 x 256 x 362 ran 118 ms with them, 101 ms without)
 #define RT_COL(NC)                                                                             \
     case NC:                                                                                   \
-        hipLaunchKernelGGL((k_column<Real, NC, VWLDS>), dim3(CI.grid), dim3(kColBlock), lds, s, \
+        hipLaunchKernelGGL((k_column<Real, NC, sizeof(Real) == 4,                              \
+                                     sizeof(Real) == 4 && NC <= 3>),                           \
+                           dim3(CI.grid), dim3(kColBlock), lds, s,                             \
                            G, CI, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, \
                            rho, u, ka, ks, dt, dT0, P.sums, P.noroot,                          \
                            static_cast<Real *>(Istar));                                        \
@@ -497,7 +559,10 @@ bool column_config(rt_grid *g, int seglen_hint, bool force) {
     const int nch = (G.nang + kWave - 1) / kWave;
     if (nch > (real == 4 ? 6 : (force ? 4 : 2))) return false;
     CI.own_stride = (G.nang + 3) / 4 * 4;
-    CI.wave_lds = CI.own_stride + (real == 4 ? 2 * G.nedge : 0);
+    // as the launcher instantiates: FP32 edge weights in LDS, FP32
+    // neighbour-row buffer [8][nch][64] up to three chunks
+    CI.wave_lds = CI.own_stride + (real == 4 ? 2 * G.nedge : 0) +
+                  (real == 4 && nch <= 3 ? 8 * nch * kWave : 0);
     // within the default dynamic LDS limit (no attribute call needed)
     return (size_t)kColWaves * CI.wave_lds * real <= 64 * 1024;
 }

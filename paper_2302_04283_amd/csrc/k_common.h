@@ -263,6 +263,11 @@ __device__ __forceinline__ double half_slope(double a, double b, double c) {
     return prod > 0.0 ? (2.0 * prod) / (dm + dp) * 0.5 : 0.0;
 }
 
+// a / b: in FP32 with the hardware reciprocal (about 1 ulp), in FP64 an
+// IEEE division
+__device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+
 // Positive root of B4 T^4 + B1 T + B0 (Sec. 2.5) by Newton's method started
 // at T_hi = min(-B0/B1, (-B0/B4)^(1/4)) >= root: the polynomial is
 // increasing and convex on T >= 0, so the iterates decrease monotonically to

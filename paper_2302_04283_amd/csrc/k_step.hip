@@ -166,12 +166,12 @@ __device__ __forceinline__ void step_body(DevGrid G, const Real *__restrict__ Ii
                 const Real qn = qrow[n];
                 Real Qs = qn * Ic;
                 if (EXT && st.Ib) Qs = Real(st.gI) * Qs + Real(st.gB) * (qn * st.Ib[x.c * N + n]);
-                Qs = Qs - dtR * ivol * dq[ch] - dtR * div / Real(G.domega[n]);
+                Qs = Qs - dtR * ivol * dq[ch] - quot(dtR * div, Real(G.domega[n]));
                 if (mrow[n]) {
                     me_acc -= (EXT ? st.wS : 1.0) * volD * G.domega[n] * (double)Qs;
                     continue;
                 }
-                Is[ch] = Qs / qn;
+                Is[ch] = quot(Qs, qn);
             }
         }
         if (Istar) {

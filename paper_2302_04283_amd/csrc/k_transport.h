@@ -64,12 +64,6 @@ __device__ __forceinline__ Real nbr(const DevGrid &G, const Real *__restrict__ I
     return I[(x.c + (long long)(edge - coord) * stride) * G.nang + n];
 }
 
-template <typename Real>
-__device__ __forceinline__ Real van_leer(Real dm, Real dp) {
-    Real prod = dm * dp;
-    return prod > Real(0) ? Real(2) * prod / (dm + dp) : Real(0);
-}
-
 // I* of direction n in cell x after the flux divergence (Sec. 2.2 gray
 // integral form) and primitive recovery, zero where masked.  Adds the
 // luminosity-face and masked-energy contributions to the accumulators.
@@ -90,21 +84,21 @@ __device__ __forceinline__ Real transport_dir(const DevGrid &G, const Real *__re
         v[2] = Ic;
         v[1] = nbr(G, Iin, x, a, -1, n);
         v[3] = nbr(G, Iin, x, a, +1, n);
-        Real dlm = Real(0), dl0 = Real(0), dlp = Real(0);
+        Real hlm = Real(0), hl0 = Real(0), hlp = Real(0);
         if (G.recon == RT_RECON_PLM) {
             v[0] = nbr(G, Iin, x, a, -2, n);
             v[4] = nbr(G, Iin, x, a, +2, n);
-            dlm = van_leer(v[1] - v[0], v[2] - v[1]);
-            dl0 = van_leer(v[2] - v[1], v[3] - v[2]);
-            dlp = van_leer(v[3] - v[2], v[4] - v[3]);
+            hlm = half_slope(v[0], v[1], v[2]);
+            hl0 = half_slope(v[1], v[2], v[3]);
+            hlp = half_slope(v[2], v[3], v[4]);
         }
         const int flo = face_geo(G, a, coord, x);
         const int fhi = face_geo(G, a, coord + 1, x);
         const Real *C = static_cast<const Real *>(G.C[a]);
         const int slo = G.sgn[a][(size_t)flo * N + n];
         const int shi = G.sgn[a][(size_t)fhi * N + n];
-        const Real ulo = slo > 0 ? v[1] + Real(0.5) * dlm : (slo < 0 ? v[2] - Real(0.5) * dl0 : Real(0));
-        const Real uhi = shi > 0 ? v[2] + Real(0.5) * dl0 : (shi < 0 ? v[3] - Real(0.5) * dlp : Real(0));
+        const Real ulo = slo > 0 ? v[1] + hlm : (slo < 0 ? v[2] - hl0 : Real(0));
+        const Real uhi = shi > 0 ? v[2] + hl0 : (shi < 0 ? v[3] - hlp : Real(0));
         const Real Flo = C[(size_t)flo * N + n] * ulo;
         const Real Fhi = C[(size_t)fhi * N + n] * uhi;
         dq += Fhi - Flo;
@@ -128,12 +122,12 @@ __device__ __forceinline__ Real transport_dir(const DevGrid &G, const Real *__re
         }
     }
     const Real qn = q[(size_t)x.gc * N + n];
-    const Real Qs = qn * Ic - dtR * ivol * dq - dtR * div / Real(G.domega[n]);
+    const Real Qs = qn * Ic - dtR * ivol * dq - quot(dtR * div, Real(G.domega[n]));
     if (G.mask[(size_t)x.gc * N + n]) {
         me_acc -= G.volD[x.gc] * G.domega[n] * (double)Qs;
         return Real(0);
     }
-    return Qs / qn;
+    return quot(Qs, qn);
 }
 
 // Row pointers of one axis for the general step: the cell is uniform across
@@ -263,15 +257,15 @@ __device__ __forceinline__ Real axis_div(const DevGrid &G, const AxisRows<Real> 
         }
         v[slot] = val;
     }
-    Real dlm = Real(0), dl0 = Real(0), dlp = Real(0);
+    Real hlm = Real(0), hl0 = Real(0), hlp = Real(0);
     if (plm) {
-        dlm = van_leer(v[1] - v[0], v[2] - v[1]);
-        dl0 = van_leer(v[2] - v[1], v[3] - v[2]);
-        dlp = van_leer(v[3] - v[2], v[4] - v[3]);
+        hlm = half_slope(v[0], v[1], v[2]);
+        hl0 = half_slope(v[1], v[2], v[3]);
+        hlp = half_slope(v[2], v[3], v[4]);
     }
     const int slo = R.Slo[n], shi = R.Shi[n];
-    Real ulo = slo > 0 ? v[1] + Real(0.5) * dlm : (slo < 0 ? v[2] - Real(0.5) * dl0 : Real(0));
-    Real uhi = shi > 0 ? v[2] + Real(0.5) * dl0 : (shi < 0 ? v[3] - Real(0.5) * dlp : Real(0));
+    Real ulo = slo > 0 ? v[1] + hlm : (slo < 0 ? v[2] - hl0 : Real(0));
+    Real uhi = shi > 0 ? v[2] + hl0 : (shi < 0 ? v[3] - hlp : Real(0));
     if constexpr (TAU) {
         double nb[3];
 #pragma unroll
