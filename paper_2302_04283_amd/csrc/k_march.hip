@@ -186,10 +186,14 @@ void k_march(
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int n = a + SW * k;
-            const Real v = src[k < NC - 1 ? n : min(n, N - 1)];
+            dst[k] = src[k < NC - 1 ? n : min(n, N - 1)];
+        }
+        if (test != 0) {
             // ghost of an outflow/vacuum boundary: copy for directions leaving
-            // through it (all bits of `test` set; test = 0 always copies)
-            dst[k] = ((s_bits[n] & test) == test) ? v : Real(0);
+            // through it (all bits of `test` set), zero for the others
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                dst[k] = ((s_bits[a + SW * k] & test) == test) ? dst[k] : Real(0);
         }
     };
     // this lane group's halo cells: source rows and outflow tests
