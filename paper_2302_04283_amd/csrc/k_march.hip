@@ -267,6 +267,25 @@ void k_march(
         fm[k] = (b & kMasked) != 0;
     }
 
+    // FP32: the lane's per-direction coefficients (q, 1/q, signed C/dV per
+    // axis) held in registers for the whole segment where that keeps the
+    // resident waves per SIMD (not for 4 or 8 directions per lane); FP64, at
+    // its register limit, reads them from LDS
+    constexpr bool REGTAB = sizeof(Real) == 4 && NC != 4 && NC != 8;
+    Real tq[REGTAB ? NC : 1], tiq[REGTAB ? NC : 1], tcx[REGTAB ? NC : 1], tcy[REGTAB ? NC : 1],
+        tcz[REGTAB ? NC : 1];
+    if constexpr (REGTAB) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int n = a + SW * k;
+            tq[k] = s_tab[n];
+            tiq[k] = s_tab[NP + n];
+            tcx[k] = s_tab[2 * NP + n];
+            tcy[k] = s_tab[3 * NP + n];
+            tcz[k] = s_tab[4 * NP + n];
+        }
+    }
+
     double lum_acc = 0.0, me_acc = 0.0;
     int nr_acc = 0;
 
@@ -338,7 +357,9 @@ void k_march(
                 const Real Ibz = nz ? zc[k] : zup;
                 zc[k] = zup;
                 // signed coefficients: +-C/dV with the sign of the motion
-                const Real cx = s_tab[2 * NP + n], cy = s_tab[3 * NP + n], cz = s_tab[4 * NP + n];
+                const Real cx = REGTAB ? tcx[REGTAB ? k : 0] : s_tab[2 * NP + n];
+                const Real cy = REGTAB ? tcy[REGTAB ? k : 0] : s_tab[3 * NP + n];
+                const Real cz = REGTAB ? tcz[REGTAB ? k : 0] : s_tab[4 * NP + n];
                 const Real dq = fma(cz, Ibz - Iaz, fma(cy, Iby - Iay, cx * (Ibx - Iax)));
                 Real Qb = Ic;
                 if constexpr (STG) {
@@ -346,11 +367,9 @@ void k_march(
                         Qb = Real(st.gI) * Ic +
                              Real(st.gB) * ((k < NC - 1 || n < N) ? st.Ib[cidx * N + n] : Real(0));
                 }
-                const Real Qs = fma(-dtR, dq, s_tab[n] * Qb);
-                if constexpr (sizeof(Real) == 4)
-                    Is[k] = Qs * s_tab[NP + n];
-                else
-                    Is[k] = Qs / s_tab[n];
+                const int kt = REGTAB ? k : 0;
+                const Real Qs = fma(-dtR, dq, (REGTAB ? tq[kt] : s_tab[n]) * Qb);
+                Is[k] = REGTAB ? Qs * tiq[kt] : Qs / s_tab[n];
                 if (doM) {
                     const bool msk = fm[k];
                     me_acc -= msk ? (STG ? st.wS : 1.0) * vol * s_dom_all[n] * (double)Qs : 0.0;
