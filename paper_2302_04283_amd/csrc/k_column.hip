@@ -40,6 +40,7 @@ namespace {
 
 constexpr int kColBlock = 256;
 constexpr int kColMaxAng = 6 * kWave;   // largest direction count of the column kernel
+constexpr int kColBand = 16;            // rows along axis 1 of a band of workgroups
 // resident waves per SIMD the register allocation is held to: the column's
 // geometry and plane queue live in registers, about 25 VGPRs per direction
 // chunk in FP32 and 40 in FP64 on top of the coupling's working set
@@ -109,17 +110,28 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     // XCD-aware logical block: the hardware hands block b to XCD b % 8
     const int per = gridDim.x / 8;
     const int logical = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    const long long work = (long long)logical * kColWaves + wave;
-    const bool active = work < CI.nwork;
+    // a workgroup's four waves take four neighbouring columns along axis 0;
+    // workgroups run through bands of kColBand rows along axis 1, quad by
+    // quad with the rows of the band fastest, so the axis-1 neighbours (and,
+    // a band's height later, the axis-0 neighbours) of a column march at
+    // the same time and its neighbour rows are read from L2
     const long long pcells = (long long)G.n0 * G.n1;
-    int i = 0, j = 0, z0 = 0, z1 = 0;
+    const int nq = (G.n0 + kColWaves - 1) / kColWaves;
+    const long long per_seg = (long long)nq * G.n1;
+    const int seg = (int)(logical / per_seg);
+    const int r = (int)(logical % per_seg);
+    const int nband = (G.n1 + kColBand - 1) / kColBand;
+    const int band = min(r / (nq * kColBand), nband - 1);
+    const int h = min(kColBand, G.n1 - band * kColBand);   // rows of this band
+    const int t = r - band * nq * kColBand;
+    int i = (t / h) * kColWaves + wave, j = band * kColBand + t % h, z0 = 0, z1 = 0;
+    const bool active = seg < CI.nseg && i < G.n0;
     if (active) {
-        i = (int)(work % G.n0);
-        const long long rest = work / G.n0;
-        j = (int)(rest % G.n1);
-        const int seg = (int)(rest / G.n1);
         z0 = seg * CI.seglen;
         z1 = min(G.n2, z0 + CI.seglen);
+    } else {
+        i = 0;
+        j = 0;
     }
     Cell x;
     x.i = i;
@@ -546,7 +558,9 @@ bool column_config(rt_grid *g, int seglen_hint, bool force) {
     seglen = std::min<long long>(seglen, G.n2);
     const long long nseg = (G.n2 + seglen - 1) / seglen;
     const long long nwork = cols * nseg;
-    const long long blocks = (nwork + kColWaves - 1) / kColWaves;
+    // one workgroup per quad of columns along axis 0 (the last quad of a row
+    // may be partly idle) per row and segment
+    const long long blocks = (long long)((G.n0 + kColWaves - 1) / kColWaves) * G.n1 * nseg;
     if (blocks >= (1LL << 30)) return false;
     CI.seglen = (int)seglen;
     CI.nseg = (int)nseg;
