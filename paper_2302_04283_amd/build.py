@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpaper_rt.so")
 SOURCES = ["csrc/rt_api.cpp", "csrc/rt_geodesic.cpp", "csrc/rt_latlong.cpp", "csrc/rt_mapr.cpp", "csrc/rt_geometry.cpp",
            "csrc/k_step.hip", "csrc/k_march.hip", "csrc/k_column.hip", "csrc/k_adjoint.hip",
-           "csrc/k_adj_march.hip", "csrc/k_gas.hip"]
+           "csrc/k_adj_march.hip", "csrc/k_adj_column.hip", "csrc/k_gas.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -12,14 +12,15 @@
 //                  FP64 angle sums by their own adjoint sums.  Writes
 //                  psi = (dJ/dI*) / (n^0 n_0) per cell-direction.
 //   k_adj_transport (one lane per cell-direction; the tiled k_adj_march in
-//                  its place for spatially uniform geometry) gathers over the faces
+//                  its place for spatially uniform geometry, the column march
+//                  k_adj_column for geometry independent of axis 2) gathers over the faces
 //                  whose upwind value depends on the cell (radius 2): the
 //                  direct term, the upwind PLM fluxes with the van Leer
 //                  limiter's Jacobian on the branch the forward took, the
 //                  angular upwind fluxes, and the luminosity seed.
 #include <hip/hip_runtime.h>
 
-#include "k_transport.h"
+#include "k_adj_common.h"
 
 namespace rt {
 namespace {
@@ -345,24 +346,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real 
                     const int u = s > 0 ? fo - 1 : fo;       // upwind cell, relative to x
                     if (u < -1 || u > 1) continue;
                     if (!periodic && (coord + u < 0 || coord + u >= len)) continue;  // ghost upwind
-                    // d I_up / d I_x, I_up = I_u +- delta_u / 2
-                    Real d = u == 0 ? Real(1) : Real(0);
+                    // d V / d I_x (helpers shared with the column adjoint)
+                    Real dh = Real(0);
                     if (plm) {
-                        const Real dm = v[u + 2] - v[u + 1], dp = v[u + 3] - v[u + 2];
-                        const Real prod = dm * dp;
-                        if (prod > Real(0)) {
-                            const Real den = dm + dp;
-                            const Real Dm = Real(2) * dp * dp / (den * den);   // d delta / d dm
-                            const Real Dp = Real(2) * dm * dm / (den * den);   // d delta / d dp
-                            // position of x in (u-1, u, u+1)
-                            const Real dd = u == 1 ? -Dm : (u == 0 ? Dm - Dp : Dp);
-                            d += (s > 0 ? Real(0.5) : Real(-0.5)) * dd;
-                        }
+                        Real hx, hy;
+                        half_slope_partials(v[u + 1], v[u + 2], v[u + 3], hx, hy);
+                        dh = dh_at(u, hx, hy);
                     }
+                    const Real d = face_weight(u == 0, s > 0, plm, dh);
                     // dJ/dF: the face is the upper face of cell fo-1 and the lower face of cell fo
-                    Real lF = dtR * (ps[fo + 2] * iv[fo + 2] - ps[fo + 1] * iv[fo + 1]);
-                    if (fon[f]) lF += Real((G.lum_side == 1 ? -1.0 : 1.0) * lum_weight * dt * G.domega[n]);
-                    lam[ch] += lF * Crow[f][n] * d;
+                    Real lF = face_adjoint(dtR, ps[fo + 2], iv[fo + 2], ps[fo + 1], iv[fo + 1]);
+                    if (fon[f]) lF += lum_seed<Real>(G, lum_weight, dt, n);
+                    face_add(lam[ch], lF, Crow[f][n], d);
                 }
             }
         }
@@ -380,9 +375,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real 
                     const bool up = G.adj_s[n * kMaxNbr + s] > 0 ? vv > Real(0) : vv < Real(0);
                     if (!up) continue;
                     const int lo = G.edge_lo[e], hi = G.edge_hi[e];
-                    const Real lF = -dtR * (psi[x.c * N + lo] / Real(G.domega[lo]) -
-                                            psi[x.c * N + hi] / Real(G.domega[hi]));
-                    lam[ch] += lF * ww;
+                    edge_add(lam[ch], dtR, psi[x.c * N + lo], Real(1.0 / G.domega[lo]),
+                             psi[x.c * N + hi], Real(1.0 / G.domega[hi]), ww);
                 }
             }
             lamI0[x.c * N + n] = lam[ch];
@@ -437,6 +431,7 @@ int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
 #undef RT_LAUNCH
     if (hipGetLastError() != hipSuccess) return RT_EDEVICE;
     if (g->march.enabled) return launch_adj_march(g, s, Iin, psi, dt, lum_weight, lamI0);
+    if (g->column.enabled) return launch_adj_column(g, s, Iin, psi, dt, lum_weight, lamI0);
 #define RT_LAUNCH2(NC)                                                                         \
     case NC:                                                                                   \
         hipLaunchKernelGGL((k_adj_transport<Real, NC>), dim3(nblk), dim3(kBlock), 0, s, G, in,    \

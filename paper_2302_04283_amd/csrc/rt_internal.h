@@ -190,6 +190,10 @@ int launch_adjoint(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin
                    const void *Istar);
 int launch_adj_march(rt_grid *g, hipStream_t s, const void *Iin, const void *psi, double dt,
                      double lum_weight, void *lamI0);
+// k_adj_column.hip: the transport adjoint with the column layout (used where
+// the forward step uses k_column)
+int launch_adj_column(rt_grid *g, hipStream_t s, const void *Iin, const void *psi, double dt,
+                      double lum_weight, void *lamI0);
 // k_column.hip
 bool column_config(rt_grid *g, int seglen_hint, bool force);
 int launch_column(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
