@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpaper_rt.so")
-SOURCES = ["csrc/rt_api.cpp", "csrc/rt_geodesic.cpp", "csrc/rt_latlong.cpp", "csrc/rt_mapr.cpp", "csrc/rt_geometry.cpp",
+SOURCES = ["csrc/rt_api.cpp", "csrc/rt_desc.cpp", "csrc/rt_geodesic.cpp", "csrc/rt_latlong.cpp", "csrc/rt_mapr.cpp", "csrc/rt_geometry.cpp",
            "csrc/k_step.hip", "csrc/k_march.hip", "csrc/k_column.hip", "csrc/k_adjoint.hip",
            "csrc/k_adj_march.hip", "csrc/k_adj_column.hip", "csrc/k_gas.hip"]
 

@@ -52,6 +52,14 @@ constexpr int kAcMaxAng = 6 * kWave;      // as the forward column kernel
 constexpr unsigned kAzP = 1u << 16, kAzN = 1u << 17, kAMsk = 1u << 18;
 constexpr int kAGhostShift = 20;
 
+// element n of a row at a wave-uniform address: a scalar base plus a 32-bit
+// lane byte offset (the global_load "saddr" form, one VGPR per offset)
+template <typename Real>
+__device__ __forceinline__ const Real *at_lane(const Real *row, unsigned n) {
+    return reinterpret_cast<const Real *>(reinterpret_cast<const char *>(row) +
+                                          (unsigned)(n * sizeof(Real)));
+}
+
 __device__ __forceinline__ void acol_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -59,13 +67,15 @@ __device__ __forceinline__ void acol_wave_sync() {
 }
 
 // the four faces of one axis for one direction: fb holds the axis's eight
-// face bits, fon the luminosity faces (bit f); v, ps, iv are I, psi and 1/dV
-// at offsets -2 .. +2; C the face coefficients
+// face bits, fon the luminosity faces (bit f, wave-uniform), seed the
+// luminosity seed of the direction; v, ps, iv are I, psi and 1/dV at offsets
+// -2 .. +2; C the face coefficients.  Branch-free: every face term is
+// formed and kept by a select where the face contributes, so the sum is
+// bit-identical to the general gather's conditional additions.
 template <typename Real>
 __device__ __forceinline__ void adj_axis(Real &lam, const Real (&v)[5], const Real (&ps)[5],
                                          const Real (&iv)[5], const Real (&C)[4], unsigned fb,
-                                         unsigned fon, bool plm, Real dtR, const DevGrid &G,
-                                         double lum_weight, double dt, int n) {
+                                         unsigned fon, Real seed, bool plm, Real dtR) {
     // limiter partials of the upwind cells u = -1, 0, +1 (index u + 1)
     Real hx[3], hy[3];
 #pragma unroll
@@ -77,7 +87,6 @@ __device__ __forceinline__ void adj_axis(Real &lam, const Real (&v)[5], const Re
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         const bool P = (fb >> (2 * f)) & 1u, Nn = (fb >> (2 * f + 1)) & 1u;
-        if (!P && !Nn) continue;
         const int fo = f - 1;
         const int u = P ? fo - 1 : fo;
         // index u + 1 of the limiter partials, for either sign (the sign
@@ -87,13 +96,13 @@ __device__ __forceinline__ void adj_axis(Real &lam, const Real (&v)[5], const Re
         if (plm) dh = dh_at(u, P ? hx[iP] : hx[iN], P ? hy[iP] : hy[iN]);
         const Real d = face_weight(u == 0, P, plm, dh);
         Real lF = face_adjoint(dtR, ps[fo + 2], iv[fo + 2], ps[fo + 1], iv[fo + 1]);
-        if ((fon >> f) & 1u) lF += lum_seed<Real>(G, lum_weight, dt, n);
-        face_add(lam, lF, C[f], d);
+        if ((fon >> f) & 1u) lF += seed;
+        Real t = lam;
+        face_add(t, lF, C[f], d);
+        lam = (P || Nn) ? t : lam;
     }
 }
 
-// NCW: 64-direction chunks per wave; DMA: neighbour rows and the psi row
-// moved into LDS by global_load_lds (FP32)
 template <typename Real, int NCW>
 constexpr int acol_waves() {
     return sizeof(Real) == 4 && NCW == 1 ? 3 : 2;
@@ -105,7 +114,9 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
                                                          const Real *__restrict__ psi, double dt,
                                                          double lum_weight, Real *__restrict__ lam) {
     const int lane = threadIdx.x % kWave;
-    const int wave = threadIdx.x / kWave;
+    // wave-uniform (scalar registers): the column and every row address
+    // derived from it, so loads take a scalar base plus a lane offset
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int N = G.nang;
     const int nchT = (N + kWave - 1) / kWave;
     __shared__ int s_adj[kAcMaxAng * kMaxNbr];
@@ -269,50 +280,51 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
             if (up) eu[ch] |= 1u << s;
         }
     }
+    // luminosity seed of the lane's directions (used on luminosity faces)
+    Real seed[NCW];
+#pragma unroll
+    for (int ch = 0; ch < NCW; ++ch)
+        seed[ch] = lum_seed<Real>(G, lum_weight, dt, min(lane + kWave * (cb + ch), N - 1));
     __syncthreads();   // s_adj, s_iom
     if (!active) return;
 
     const bool zper = G.bc[2][0] == RT_BC_PERIODIC;
     const int mycol = (int)x.c;
-    // plane pz of the column, I with the axis-2 boundary condition (vacuum
-    // ghosts: the edge cell for directions leaving through that face, zero
-    // otherwise), psi zero outside a non-periodic boundary
-    auto load_I = [&](int pz, Real (&dst)[NCW]) {
+    // plane pz of the column, I and psi as stored (the wrapped or edge
+    // plane), and what the axis-2 boundary condition makes of them: I keeps
+    // the edge cell only for directions leaving through that face (`need`
+    // bit; 0: kept), psi is zero outside a non-periodic boundary.  The
+    // condition is applied where a plane enters the queue, so a prefetched
+    // plane is not waited for when it is issued.
+    auto load_raw = [&](int pz, Real (&dI)[NCW], Real (&dP)[NCW], unsigned &need, bool &inside) {
         long long zz = pz;
-        unsigned need = 0;
+        need = 0;
+        inside = true;
         if (pz < 0 || pz >= G.n2) {
             const int side = pz < 0 ? 0 : 1;
             if (zper) {
                 zz = ((pz % G.n2) + G.n2) % G.n2;
             } else {
                 need = side ? kAzP : kAzN;
+                inside = false;
                 zz = side ? G.n2 - 1 : 0;
             }
         }
-        const Real *src = Iin + (zz * pcells + mycol) * N;
+        const Real *srcI = Iin + (zz * pcells + mycol) * N;
+        const Real *srcP = psi + (zz * pcells + mycol) * N;
 #pragma unroll
         for (int ch = 0; ch < NCW; ++ch) {
-            const int n = lane + kWave * (cb + ch);
-            const Real v = src[min(n, N - 1)];
-            dst[ch] = (need == 0 || (fl[ch] & need)) ? v : Real(0);
+            const unsigned n = (unsigned)min(lane + kWave * (cb + ch), N - 1);
+            dI[ch] = *at_lane(srcI, n);
+            dP[ch] = *at_lane(srcP, n);
         }
     };
-    auto load_P = [&](int pz, Real (&dst)[NCW]) {
-        long long zz = pz;
-        bool inside = true;
-        if (pz < 0 || pz >= G.n2) {
-            if (zper) {
-                zz = ((pz % G.n2) + G.n2) % G.n2;
-            } else {
-                inside = false;
-                zz = 0;
-            }
-        }
-        const Real *src = psi + (zz * pcells + mycol) * N;
+    auto enqueue = [&](const Real (&dI)[NCW], const Real (&dP)[NCW], unsigned need, bool inside,
+                       Real (&qI)[NCW], Real (&qP)[NCW]) {
 #pragma unroll
         for (int ch = 0; ch < NCW; ++ch) {
-            const int n = lane + kWave * (cb + ch);
-            dst[ch] = inside ? src[min(n, N - 1)] : Real(0);
+            qI[ch] = (need == 0 || (fl[ch] & need)) ? dI[ch] : Real(0);
+            qP[ch] = inside ? dP[ch] : Real(0);
         }
     };
     // DMA: the sixteen neighbour rows of plane pz (this wave's chunks) and
@@ -324,15 +336,16 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
             const Real *bP = psi + (long long)pz * pcells * N;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
+                const Real *rI = bI + (long long)ncol[k] * N;
+                const Real *rP = bP + (long long)ncol[k] * N;
 #pragma unroll
                 for (int ch = 0; ch < NCW; ++ch) {
-                    const int n = min(lane + kWave * (cb + ch), N - 1);
-                    const long long off = (long long)ncol[k] * N + n;
+                    const unsigned n = (unsigned)min(lane + kWave * (cb + ch), N - 1);
                     __builtin_amdgcn_global_load_lds(
-                        bI + off, (__attribute__((address_space(3))) void *)(s_nb + (k * NCW + ch) * kWave),
+                        at_lane(rI, n), (__attribute__((address_space(3))) void *)(s_nb + (k * NCW + ch) * kWave),
                         4, 0, 0);
                     __builtin_amdgcn_global_load_lds(
-                        bP + off,
+                        at_lane(rP, n),
                         (__attribute__((address_space(3))) void *)(s_nb + ((8 + k) * NCW + ch) * kWave), 4,
                         0, 0);
                 }
@@ -341,7 +354,7 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
                 const Real *src = bP + (long long)mycol * N;
                 for (int c = 0; c < nchT; ++c)
                     __builtin_amdgcn_global_load_lds(
-                        src + min(lane + kWave * c, N - 1),
+                        at_lane(src, (unsigned)min(lane + kWave * c, N - 1)),
                         (__attribute__((address_space(3))) void *)(row + kWave * c), 4, 0, 0);
             }
         }
@@ -365,8 +378,11 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
     Real qi[5][NCW], qp[5][NCW];
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
-        load_I(z0 - 2 + p, qi[p]);
-        load_P(z0 - 2 + p, qp[p]);
+        Real dI[NCW], dP[NCW];
+        unsigned need;
+        bool inside;
+        load_raw(z0 - 2 + p, dI, dP, need, inside);
+        enqueue(dI, dP, need, inside, qi[p], qp[p]);
     }
     if constexpr (DMA) dma_plane(z0, s_row);
 
@@ -389,10 +405,9 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
         }
         // the column's plane z+3 while this one is computed
         Real ni[NCW], np[NCW];
-        if (more) {
-            load_I(z + 3, ni);
-            load_P(z + 3, np);
-        }
+        unsigned nneed = 0;
+        bool nin = true;
+        if (more) load_raw(z + 3, ni, np, nneed, nin);
         // axis-2 faces of this plane: which sign may contribute, the
         // luminosity faces, 1/dV at offsets -2 .. +2
         unsigned zv = 0, zfon = 0;
@@ -453,8 +468,7 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
                 v[2] = qi[2][ch];
                 ps[2] = qp[2][ch];
                 iv[2] = ivol;
-                adj_axis(acc[ch], v, ps, iv, C, (f >> (8 * a)) & 0xffu, fon[a], plm, dtR, G,
-                         lum_weight, dt, n);
+                adj_axis(acc[ch], v, ps, iv, C, (f >> (8 * a)) & 0xffu, fon[a], seed[ch], plm, dtR);
             }
         }
         if constexpr (DMA) {
@@ -477,22 +491,24 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
                 const Real ps[5] = {qp[0][ch], qp[1][ch], qp[2][ch], qp[3][ch], qp[4][ch]};
                 const Real C[4] = {czz[ch], czz[ch], czz[ch], czz[ch]};
                 const unsigned fb = (f & kAzP ? (zv & 0x55u) : 0u) | (f & kAzN ? (zv & 0xAAu) : 0u);
-                adj_axis(acc[ch], v, ps, ivz, C, fb, zfon, plm, dtR, G, lum_weight, dt, m);
+                adj_axis(acc[ch], v, ps, ivz, C, fb, zfon, seed[ch], plm, dtR);
             }
-            if (n >= N) continue;
             if (G.has_edges) {
+                // branch-free over the six slots: a slot past the direction's
+                // edges (record < 0, trailing) or not upwind keeps the sum
 #pragma unroll
                 for (int s = 0; s < kMaxNbr; ++s) {
-                    const int rec = s_adj[n * kMaxNbr + s];
-                    if (rec < 0) break;
-                    if (!((eu[ch] >> s) & 1u)) continue;
-                    const int mm = (rec >> 15) & 0x7fff;
+                    const int rec = s_adj[m * kMaxNbr + s];
+                    const bool use = rec >= 0 && ((eu[ch] >> s) & 1u);
+                    const int mm = rec >= 0 ? (rec >> 15) & 0x7fff : m;
                     const bool is_lo = (rec >> 30) & 1;
-                    const int lo = is_lo ? n : mm, hi = is_lo ? mm : n;
-                    edge_add(acc[ch], dtR, own[lo], s_iom[lo], own[hi], s_iom[hi], ew[s][ch]);
+                    const int lo = is_lo ? m : mm, hi = is_lo ? mm : m;
+                    Real t = acc[ch];
+                    edge_add(t, dtR, own[lo], s_iom[lo], own[hi], s_iom[hi], ew[s][ch]);
+                    acc[ch] = use ? t : acc[ch];
                 }
             }
-            dst[n] = acc[ch];
+            if (n < N) dst[n] = acc[ch];
         }
         if (!DMA && G.has_edges) acol_wave_sync();   // own row read before it is rewritten
 #pragma unroll
@@ -502,9 +518,8 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
                 qi[p][ch] = qi[p + 1][ch];
                 qp[p][ch] = qp[p + 1][ch];
             }
-            qi[4][ch] = ni[ch];
-            qp[4][ch] = np[ch];
         }
+        if (more) enqueue(ni, np, nneed, nin, qi[4], qp[4]);
     }
 }
 

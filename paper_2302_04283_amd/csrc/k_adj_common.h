@@ -26,18 +26,16 @@ __device__ __forceinline__ Real inv(Real s) {
         return rcp64(s);
 }
 
-// x^2 and y^2 of the limiter h(l, m, r) (both zero on the flat branch)
+// x^2 and y^2 of the limiter h(l, m, r) (both zero on the flat branch;
+// formed on both branches and selected, so no divergent branch)
 template <typename Real>
 __device__ __forceinline__ void half_slope_partials(Real l, Real m, Real r, Real &hx, Real &hy) {
     const Real a = m - l, b = r - m;
-    hx = Real(0);
-    hy = Real(0);
-    if (a * b > Real(0)) {
-        const Real i = inv(a + b);
-        const Real x = a * i, y = b * i;
-        hx = x * x;
-        hy = y * y;
-    }
+    const Real i = inv(a + b);
+    const Real x = a * i, y = b * i;
+    const bool on = a * b > Real(0);
+    hx = on ? x * x : Real(0);
+    hy = on ? y * y : Real(0);
 }
 
 // dh_u / dI_x for the upwind cell u = -1, 0, +1 relative to x (x is the

@@ -39,7 +39,6 @@ namespace rt {
 namespace {
 
 constexpr int kColBlock = 256;
-constexpr int kColMaxAng = 6 * kWave;   // largest direction count of the column kernel
 constexpr int kColBand = 16;            // rows along axis 1 of a band of workgroups
 // resident waves per SIMD the register allocation is held to: the column's
 // geometry and plane queue live in registers, about 25 VGPRs per direction
@@ -95,17 +94,27 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     double *__restrict__ dT0, double *__restrict__ partials, int *__restrict__ nr_partial,
     Real *__restrict__ Istar) {
     const int lane = threadIdx.x % kWave;
-    const int wave = threadIdx.x / kWave;
+    // wave-uniform (scalar registers): the column and every row address
+    // derived from it
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int N = G.nang;
     const int E = G.nedge;
-    __shared__ int s_adj[kColMaxAng * kMaxNbr];
     extern __shared__ __align__(16) unsigned char s_dyn[];
+    // the direction tables every plane reads -- unit vectors, solid angles,
+    // angular-edge records -- staged once per workgroup, so the plane loop
+    // issues no global load behind the neighbour-row DMA (vector-memory
+    // counters retire in order: a later load's wait would also wait for it)
+    double *s_nhat = reinterpret_cast<double *>(s_dyn);     // [N][3]
+    double *s_dom = s_nhat + 3 * N;                          // [N]
+    int *s_adj = reinterpret_cast<int *>(s_dom + N);         // [N][6]
     // per wave: the cell's row [own_stride], the column's edge weights [2E]
     // (VWLDS), the next plane's eight neighbour rows [8][NCH][64] (DMA)
-    Real *s_own = reinterpret_cast<Real *>(s_dyn) + (size_t)wave * CI.wave_lds;
+    Real *s_own = reinterpret_cast<Real *>(s_dyn + CI.tab_bytes) + (size_t)wave * CI.wave_lds;
     Real *s_vw = s_own + CI.own_stride;
     Real *s_nb = s_vw + (VWLDS ? 2 * E : 0);
     for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
+    for (int k = threadIdx.x; k < 3 * N; k += kColBlock) s_nhat[k] = G.nhat[k];
+    for (int k = threadIdx.x; k < N; k += kColBlock) s_dom[k] = G.domega[k];
 
     // XCD-aware logical block: the hardware hands block b to XCD b % 8
     const int per = gridDim.x / 8;
@@ -210,15 +219,17 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
         for (int k = lane; k < 2 * E; k += kWave) s_vw[k] = row[k];
     }
     const Real *vwrow = VWLDS ? s_vw : vw + (size_t)x.gc * E * 2;
-    __syncthreads();   // s_adj, s_vw
+    __syncthreads();   // direction tables, s_vw
 
     double lum_acc = 0.0, me_acc = 0.0;
     int nr_acc = 0;
     if (active) {
-        // plane pz of column `col` for the lane's directions, with the axis-2
-        // boundary condition (vacuum ghosts: the edge cell for directions
-        // leaving through that face, zero otherwise)
-        auto load_row = [&](int pz, int col, Real (&dst)[NCH]) {
+        // plane pz of column `col` for the lane's directions as stored (the
+        // wrapped or edge plane), and the axis-2 boundary condition to apply
+        // to it: vacuum ghosts keep the edge cell only for directions leaving
+        // through that face (`need` bit; 0: kept as read).  Applied where the
+        // plane enters the queue, so a prefetch is not waited for at issue.
+        auto load_raw = [&](int pz, int col, Real (&dst)[NCH]) -> unsigned {
             long long zz = pz;
             unsigned need = 0;
             if (pz < 0 || pz >= G.n2) {
@@ -234,9 +245,17 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const int n = lane + kWave * ch;
-                const Real v = src[ch < NCH - 1 ? n : min(n, N - 1)];
-                dst[ch] = (need == 0 || (fl[ch] & need)) ? v : Real(0);
+                dst[ch] = src[ch < NCH - 1 ? n : min(n, N - 1)];
             }
+            return need;
+        };
+        auto apply_bc = [&](unsigned need, Real (&v)[NCH]) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                v[ch] = (need == 0 || (fl[ch] & need)) ? v[ch] : Real(0);
+        };
+        auto load_row = [&](int pz, int col, Real (&dst)[NCH]) {
+            apply_bc(load_raw(pz, col, dst), dst);
         };
         // the four neighbour rows of axis a (0 or 1) at plane pz
         auto load_axis = [&](int pz, int a, Real (&dst)[4][NCH]) {
@@ -301,9 +320,15 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
         for (int z = z0; z < z1; ++z) {
             const long long c = (long long)z * pcells + x.c;
             const bool more = z + 1 < z1;
+            if constexpr (DMA) {
+                // this plane's neighbour rows have landed in LDS (the wave's
+                // own loads: vmcnt reaches zero)
+                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+            }
             // the column's next plane while this one is computed
             Real qn[NCH];
-            if (more) load_row(z + 3, mycol, qn);
+            unsigned qneed = 0;
+            if (more) qneed = load_raw(z + 3, mycol, qn);
             // the cell's row into LDS for the angular gather
             col_wave_sync();
 #pragma unroll
@@ -318,11 +343,6 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             Real dq[NCH];
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) dq[ch] = Real(0);
-            if constexpr (DMA) {
-                // this plane's neighbour rows have landed in LDS (the wave's
-                // own loads: vmcnt reaches zero)
-                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-            }
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 Real nb[4][NCH];
@@ -352,7 +372,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     const Real Flo = (a ? cyl[ch] : cxl[ch]) * ulo;
                     const Real Fhi = (a ? cyh[ch] : cxh[ch]) * uhi;
                     if (lum_here && G.lum_axis == a && n < N)
-                        lum_acc += G.lum_side ? -G.domega[n] * (double)Fhi : G.domega[n] * (double)Flo;
+                        lum_acc += G.lum_side ? -s_dom[n] * (double)Fhi : s_dom[n] * (double)Flo;
                     dq[ch] += Fhi - Flo;
                 }
             }
@@ -378,16 +398,16 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     const Real Flo = Fz[ch], Fhi = czz[ch] * uhi;
                     Fz[ch] = Fhi;
                     if (lum_here && G.lum_axis == 2 && n < N)
-                        lum_acc += G.lum_side ? -G.domega[n] * (double)Fhi : G.domega[n] * (double)Flo;
+                        lum_acc += G.lum_side ? -s_dom[n] * (double)Fhi : s_dom[n] * (double)Flo;
                     dq[ch] += Fhi - Flo;
                 }
                 Is[ch] = Real(0);
                 if (n >= N) continue;
                 const Real div = G.has_edges ? angular_div_rec(s_adj, s_own, vwrow, n) : Real(0);
                 const Real qn_ = gq[ch];
-                const Real Qs = qn_ * Ic - dtR * ivol * dq[ch] - quot(dtR * div, Real(G.domega[n]));
+                const Real Qs = qn_ * Ic - dtR * ivol * dq[ch] - quot(dtR * div, Real(s_dom[n]));
                 if (f & kMsk) {
-                    me_acc -= volD * G.domega[n] * (double)Qs;
+                    me_acc -= volD * s_dom[n] * (double)Qs;
                     continue;
                 }
                 Is[ch] = quot(Qs, qn_);
@@ -412,13 +432,13 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             for (int ch = 0; ch < NCH; ++ch) {
                 const int n = lane + kWave * ch;
                 const int m = n < N ? n : 0;
-                const double nbr_ = u0 - fma(u1, G.nhat[3 * m], fma(u2, G.nhat[3 * m + 1], u3 * G.nhat[3 * m + 2]));
+                const double nbr_ = u0 - fma(u1, s_nhat[3 * m], fma(u2, s_nhat[3 * m + 1], u3 * s_nhat[3 * m + 2]));
                 const double nb2 = nbr_ * nbr_;
                 const double rr = rcp64(nb2 * fma(nbr_, tau, n0));
                 nbv[ch] = nbr_;
                 rrv[ch] = rr;
                 if (n >= N || (fl[ch] & kMsk)) continue;
-                const double dom = G.domega[n];
+                const double dom = s_dom[n];
                 const double Iw = (double)Is[ch] * (nb2 * dom);
                 sf[0] += Iw;
                 sf[1] = fma(n0 * nb2 * rr, Iw, sf[1]);
@@ -448,11 +468,11 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     const double dn = fma(nbr_, tau, n0);
                     const double I = (double)Is[ch];
                     const double Ip = fma(n0 * nbr_ * nbrr, I, cS * (nbrr * rr * dn));
-                    const double dI = (Ip - I) * G.domega[n];
+                    const double dI = (Ip - I) * s_dom[n];
                     sm[0] += dI;
-                    sm[1] = fma(dI, G.nhat[3 * n], sm[1]);
-                    sm[2] = fma(dI, G.nhat[3 * n + 1], sm[2]);
-                    sm[3] = fma(dI, G.nhat[3 * n + 2], sm[3]);
+                    sm[1] = fma(dI, s_nhat[3 * n], sm[1]);
+                    sm[2] = fma(dI, s_nhat[3 * n + 1], sm[2]);
+                    sm[3] = fma(dI, s_nhat[3 * n + 2], sm[3]);
                     out = Real(Ip);
                 }
                 if (beam_cell && n == G.beam_angle) out = Real(G.beam_I);
@@ -473,6 +493,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 }
             }
             if (more) {
+                apply_bc(qneed, qn);
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
                     qz[0][ch] = qz[1][ch];
@@ -515,7 +536,7 @@ int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
                     double dt, double *dT0, void *Istar, const Partials &P) {
     const ColumnInfo &CI = g->column;
     const DevGrid &G = g->dg;
-    const size_t lds = (size_t)kColWaves * CI.wave_lds * sizeof(Real);
+    const size_t lds = CI.tab_bytes + (size_t)kColWaves * CI.wave_lds * sizeof(Real);
     const int nch = (G.nang + kWave - 1) / kWave;
     // FP32: edge weights in LDS; neighbour rows by LDS DMA up to three chunks
     // (beyond, the buffers of four waves would leave one workgroup per CU:
@@ -573,12 +594,14 @@ bool column_config(rt_grid *g, int seglen_hint, bool force) {
     const int nch = (G.nang + kWave - 1) / kWave;
     if (nch > (real == 4 ? 6 : (force ? 4 : 2))) return false;
     CI.own_stride = (G.nang + 3) / 4 * 4;
+    // direction tables: unit vectors and solid angles (FP64), edge records
+    CI.tab_bytes = ((size_t)G.nang * (4 * sizeof(double) + kMaxNbr * sizeof(int)) + 15) / 16 * 16;
     // as the launcher instantiates: FP32 edge weights in LDS, FP32
     // neighbour-row buffer [8][nch][64] up to three chunks
     CI.wave_lds = CI.own_stride + (real == 4 ? 2 * G.nedge : 0) +
                   (real == 4 && nch <= 3 ? 8 * nch * kWave : 0);
     // within the default dynamic LDS limit (no attribute call needed)
-    return (size_t)kColWaves * CI.wave_lds * real <= 64 * 1024;
+    return CI.tab_bytes + (size_t)kColWaves * CI.wave_lds * real <= 64 * 1024;
 }
 
 int launch_column(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,

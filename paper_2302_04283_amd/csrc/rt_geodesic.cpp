@@ -9,7 +9,7 @@
 #include <stdexcept>
 #include <utility>
 
-#include "rt_internal.h"
+#include "rt_host.h"
 
 namespace rt {
 namespace {

@@ -17,7 +17,7 @@
 #include <cstring>
 #include <sstream>
 
-#include "rt_internal.h"
+#include "rt_host.h"
 
 namespace rt {
 namespace {

@@ -10,7 +10,7 @@
 #include <cmath>
 #include <stdexcept>
 
-#include "rt_internal.h"
+#include "rt_host.h"
 
 namespace rt {
 

@@ -139,59 +139,67 @@ def _dev(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def make_desc(prob, precision, beam_angle=None):
+    """The rt_grid_desc of a problem and the host arrays it points into
+    (keep them alive while the descriptor is in use)."""
+    keep = []
+
+    def arr(x, dtype=np.float64):
+        a = np.ascontiguousarray(x, dtype=dtype)
+        keep.append(a)
+        return a
+
+    d = RtGridDesc()
+    for a in range(3):
+        d.n[a] = int(prob.n[a])
+        d.geo_extent[a] = int(prob.geo_extent[a])
+        d.bc[a][0] = int(prob.bc[a][0])
+        d.bc[a][1] = int(prob.bc[a][1])
+        d.x_faces[a] = _ptr(arr(prob.x_faces[a]))
+        d.area[a] = _ptr(arr(prob.area[a]))
+        d.gcov_f[a] = _ptr(arr(prob.gcov_f[a]))
+        d.tet_f[a] = _ptr(arr(prob.tet_f[a]))
+    d.nlev = int(prob.nlev)
+    d.precision = int(precision)
+    d.recon = int(prob.recon)
+    d.lum_axis = int(prob.lum_axis)
+    d.lum_side = int(prob.lum_side)
+    d.n0_crit = float(prob.n0_crit)
+    d.a_rad = float(prob.a_rad)
+    d.gamma_gas = float(prob.gamma_gas)
+    d.kb_mu_mp = float(prob.kb_mu_mp)
+    d.integrator = int(getattr(prob, "integrator", 1))
+    d.tau_coeff = float(getattr(prob, "tau_coeff", 0.0))
+    d.rad_velocity = int(getattr(prob, "rad_velocity", 0))
+    ll = getattr(prob, "latlong", None)
+    if ll is not None:
+        d.n_zeta, d.n_psi = int(ll[0]), int(ll[1])
+    d.ang_recon = int(getattr(prob, "ang_recon", 0))
+    d.kernel = int(getattr(prob, "kernel", 0))
+    d.seglen = int(getattr(prob, "seglen", 0))
+    d.vol = _ptr(arr(prob.vol))
+    d.gcov_c = _ptr(arr(prob.gcov_c))
+    d.dgcov_c = _ptr(arr(prob.dgcov_c))
+    d.tet_c = _ptr(arr(prob.tet_c))
+    d.dtet_c = _ptr(arr(prob.dtet_c))
+    if getattr(prob, "beam_mask", None) is not None:
+        bm = arr(prob.beam_mask, np.uint8)
+        d.beam_mask = bm.ctypes.data_as(C.POINTER(C.c_uint8))
+        d.beam_I = float(prob.beam_I)
+        d.beam_angle = int(beam_angle)
+    return d, keep
+
+
 class Grid:
     """A problem's device tables; ``step``/``moments`` launch on the current stream."""
 
     def __init__(self, prob, precision=RT_F32, device: int = 0):
         import torch  # noqa: F401  (device memory comes from torch)
         lib = load()
-        keep = []
-
-        def arr(x, dtype=np.float64):
-            a = np.ascontiguousarray(x, dtype=dtype)
-            keep.append(a)
-            return a
-
-        d = RtGridDesc()
-        for a in range(3):
-            d.n[a] = int(prob.n[a])
-            d.geo_extent[a] = int(prob.geo_extent[a])
-            d.bc[a][0] = int(prob.bc[a][0])
-            d.bc[a][1] = int(prob.bc[a][1])
-            d.x_faces[a] = _ptr(arr(prob.x_faces[a]))
-            d.area[a] = _ptr(arr(prob.area[a]))
-            d.gcov_f[a] = _ptr(arr(prob.gcov_f[a]))
-            d.tet_f[a] = _ptr(arr(prob.tet_f[a]))
-        d.nlev = int(prob.nlev)
-        d.precision = int(precision)
-        d.recon = int(prob.recon)
-        d.lum_axis = int(prob.lum_axis)
-        d.lum_side = int(prob.lum_side)
-        d.n0_crit = float(prob.n0_crit)
-        d.a_rad = float(prob.a_rad)
-        d.gamma_gas = float(prob.gamma_gas)
-        d.kb_mu_mp = float(prob.kb_mu_mp)
-        d.integrator = int(getattr(prob, "integrator", 1))
-        d.tau_coeff = float(getattr(prob, "tau_coeff", 0.0))
-        d.rad_velocity = int(getattr(prob, "rad_velocity", 0))
-        ll = getattr(prob, "latlong", None)
-        if ll is not None:
-            d.n_zeta, d.n_psi = int(ll[0]), int(ll[1])
-        d.ang_recon = int(getattr(prob, "ang_recon", 0))
-        d.kernel = int(getattr(prob, "kernel", 0))
-        d.seglen = int(getattr(prob, "seglen", 0))
-        d.vol = _ptr(arr(prob.vol))
-        d.gcov_c = _ptr(arr(prob.gcov_c))
-        d.dgcov_c = _ptr(arr(prob.dgcov_c))
-        d.tet_c = _ptr(arr(prob.tet_c))
-        d.dtet_c = _ptr(arr(prob.dtet_c))
         self.beam_angle = None
         if getattr(prob, "beam_mask", None) is not None:
-            bm = arr(prob.beam_mask, np.uint8)
-            d.beam_mask = bm.ctypes.data_as(C.POINTER(C.c_uint8))
-            d.beam_I = float(prob.beam_I)
             self.beam_angle = beam_direction(prob.nlev, getattr(prob, "latlong", None))
-            d.beam_angle = self.beam_angle
+        d, keep = make_desc(prob, precision, self.beam_angle)
         h = C.c_void_p()
         _check(lib.rt_init_grid(C.byref(d), int(device), C.byref(h)))
         self._h = h
