@@ -414,14 +414,9 @@ int launch_one(rt_grid *g, hipStream_t s, const Real *Iin, const Real *psi, doub
     const int nchunk = (g->dg.nang + NP - 1) / NP;
     const int P = march_pstride(g->precision, NP);
     const size_t lds = (size_t)NP * (6 * sizeof(Real) + 1) + 2 * (size_t)kPlane * P * sizeof(Real);
-    static bool lds_set = false;
-    if (!lds_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_march<Real, SW, NC>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) != hipSuccess)
-            return RT_EDEVICE;
-        lds_set = true;
-    }
     if (lds > 150 * 1024) return RT_EINVAL;
+    if (ensure_dynamic_lds(reinterpret_cast<const void *>(&k_adj_march<Real, SW, NC>), lds) != RT_OK)
+        return RT_EDEVICE;
     const long long total = (long long)M.nwork * nchunk;
     if (total >= (1LL << 30)) return RT_EINVAL;
     const int grid = (int)((total + 7) / 8 * 8);

@@ -72,6 +72,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         v.T = Tin[c];
         v.lT = lamT1[c];
     };
+    // unit vectors and solid angles, staged per workgroup: the cell loop
+    // then issues no global load of them behind the next cell's prefetch
+    // (vector-memory counters retire in order, so such a load's wait would
+    // also wait for the prefetch)
+    extern __shared__ double s_tab[];
+    double *s_nh = s_tab;          // [N][3]
+    double *s_dom = s_tab + 3 * N; // [N]
+    for (int k = threadIdx.x; k < 3 * N; k += kBlock) s_nh[k] = G.nhat[k];
+    for (int k = threadIdx.x; k < N; k += kBlock) s_dom[k] = G.domega[k];
+    __syncthreads();
     In cur{}, nxt{};
     {
         const long long c0 = (long long)blockIdx.x * kCellsPerBlock + grp;
@@ -81,10 +91,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     for (int cw = grp; cw < kCellsPerBlock; cw += kGroups) {
         const long long cc = (long long)blockIdx.x * kCellsPerBlock + cw;
         if (cc >= ncell) break;
-        if constexpr (!RECOMP) {
-            const long long cn = cc + kGroups;
-            if (cw + kGroups < kCellsPerBlock && cn < ncell) fetch(cn, nxt);
-        }
         Cell x;
         if constexpr (RECOMP) {
             x = make_cell(G, cc);
@@ -102,6 +108,28 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
                 x.gc = ((G.g2 > 1 ? x.k : 0) * G.g1 + (G.g1 > 1 ? x.j : 0)) * G.g0 +
                        (G.g0 > 1 ? x.i : 0);
             }
+        }
+        // this cell's geometry rows, beam flag and gradient accumulators, read
+        // before the next cell's prefetch is issued (so their waits do not
+        // include it)
+        // (the mask where the registers allow, q too with one cell per
+        // wavefront; otherwise they are read where they are used)
+        constexpr bool kMK = SW == 64 || NCH <= 6;
+        constexpr bool kQ = SW == 64;
+        unsigned char mk[NCH];
+        Real qv[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int m = min(lane + SW * ch, N - 1);
+            if constexpr (kMK) mk[ch] = G.mask[(size_t)x.gc * N + m];
+            if constexpr (kQ) qv[ch] = q[(size_t)x.gc * N + m];
+        }
+        const double n0 = G.n0u[x.gc];
+        const int bm = G.beam != nullptr ? (int)G.beam[x.c] : 0;
+        const double ga = gka ? gka[x.c] : 0.0, gs = gks ? gks[x.c] : 0.0;
+        if constexpr (!RECOMP) {
+            const long long cn = cc + kGroups;
+            if (cw + kGroups < kCellsPerBlock && cn < ncell) fetch(cn, nxt);
         }
         if constexpr (RECOMP) {
 #pragma unroll
@@ -132,21 +160,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         const double rh = cur.rho;
         const double aa = cur.ka * rh, as = cur.ks * rh;
         const double tau = (aa + as) * dt;
-        const double n0 = G.n0u[x.gc];
         double nbv[NCH], rrv[NCH];
         bool live[NCH];
         double sf[3] = {0.0, 0.0, 0.0};   // Em, A1, A2
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + SW * ch;
-            live[ch] = n < N && !G.mask[(size_t)x.gc * N + (n < N ? n : 0)];
+            live[ch] = n < N && !(kMK ? mk[ch] : G.mask[(size_t)x.gc * N + (n < N ? n : 0)]);
             const int m = live[ch] ? n : 0;
-            const double nb = u0 - fma(u1, G.nhat[3 * m], fma(u2, G.nhat[3 * m + 1], u3 * G.nhat[3 * m + 2]));
+            const double nb = u0 - fma(u1, s_nh[3 * m], fma(u2, s_nh[3 * m + 1], u3 * s_nh[3 * m + 2]));
             const double nb2 = nb * nb;
             const double rr = rcp64(nb2 * fma(nb, tau, n0));
             nbv[ch] = nb;
             rrv[ch] = rr;
-            const double dom = live[ch] ? G.domega[m] : 0.0;   // zero weight: masked or padding
+            const double dom = live[ch] ? s_dom[m] : 0.0;   // zero weight: masked or padding
             const double Iw = (double)Is[ch] * (nb2 * dom);
             sf[0] += Iw;
             sf[1] = fma(n0 * nb2 * rr, Iw, sf[1]);
@@ -165,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         const double S = aa * G.a_rad * Tp3 * Tp + as * Ep;
         const double Pp = 4.0 * B4 * Tp3 + B1;
         // adjoint sums over directions: lS, X1, X2, X3
-        const bool beam_cell = G.beam != nullptr && G.beam[x.c];
+        const bool beam_cell = bm != 0;
         const double c4 = dt / kFourPi;
         double sr[4] = {0.0, 0.0, 0.0, 0.0};
         Real lpv[NCH];
@@ -178,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
             const double dn = fma(nb, tau, n0);
             const double idn = nb2 * rr;                          // 1/dn
             const double k = n0 * idn;                            // n^0/dn
-            const double dom = live[ch] ? G.domega[m] : 0.0;
+            const double dom = live[ch] ? s_dom[m] : 0.0;
             const double I = (double)Is[ch];
             const double gdir = c4 * (nb * rr) * rr * dn;         // dt/(4 pi dn nb^3)
             const double nbdn = nb * idn;                         // nb/dn
@@ -227,16 +254,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
                 const double nb = nbv[ch];
                 const double nb2 = nb * nb;
                 const double k = n0 * nb2 * rrv[ch];
-                const double w = nb2 * G.domega[n];
+                const double w = nb2 * s_dom[n];
                 const double lstar = fma(k, (double)lpv[ch], fma(lA1, k, lEm) * w);
-                out = Real(lstar * rcp64((double)q[(size_t)x.gc * N + n]));
+                out = Real(lstar * rcp64((double)(kQ ? qv[ch] : q[(size_t)x.gc * N + n])));
             }
             psi[x.c * N + n] = out;
         }
         if (lane == 0) {
             lamT0[x.c] = lTm;
-            if (gka) gka[x.c] += laa * rh;
-            if (gks) gks[x.c] += las * rh;
+            if (gka) gka[x.c] = ga + laa * rh;
+            if (gks) gks[x.c] = gs + las * rh;
         }
         if constexpr (!RECOMP) cur = nxt;
     }
@@ -402,10 +429,11 @@ int launch_adj_t(rt_grid *g, hipStream_t s, const void *Iin, const double *Tin,
     // per-direction state and the prefetched next cell in registers
     const int N = G.nang;
     int sw = N <= 176 ? 16 : (N <= 352 ? 32 : 64);
+    const size_t tab = (size_t)4 * N * sizeof(double);   // unit vectors and solid angles
     int cnc = (N + sw - 1) / sw;
 #define RT_LAUNCH(SW, NC, RC)                                                                  \
     if (sw == SW && cnc == NC)                                                                 \
-        hipLaunchKernelGGL((k_adj_couple<Real, SW, NC, RC>), dim3(nblk), dim3(kBlock), 0, s,  \
+        hipLaunchKernelGGL((k_adj_couple<Real, SW, NC, RC>), dim3(nblk), dim3(kBlock), tab, s, \
                            G, in, Tin, rho, u, ka, ks, dt, l1, lamT1, psi, lamT0, gka, gks,    \
                            static_cast<const Real *>(Istar));                                  \
     else

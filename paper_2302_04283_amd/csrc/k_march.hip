@@ -64,6 +64,8 @@ void k_march(
     __shared__ long long s_hrow[kHalo];
     __shared__ unsigned s_htest[kHalo];
     __shared__ double s_fl[kTC][8];           // fluid state of the tile's cells
+    __shared__ int s_beam[kTC];               // beam flag of the tile's cells
+    __shared__ double s_E0[16];               // E0 of the (uniform) geometry
 
     const int N = G.nang;
     // XCD-aware remap: the hardware hands block b to XCD b % 8
@@ -143,6 +145,7 @@ void k_march(
         s_hrow[h] = (long long)gy * G.n0 + gx;
         s_htest[h] = test;
     }
+    if (threadIdx.x < 16) s_E0[threadIdx.x] = G.E0[threadIdx.x];
     __syncthreads();
 
     const int lane = threadIdx.x % kWave;
@@ -156,7 +159,7 @@ void k_march(
     const bool plm = G.recon == RT_RECON_PLM;
     const double vol = M.vol;
     const double n0u = G.n0u[0];
-    const double *E0 = G.E0;
+    const double *E0 = s_E0;
     // LDS element offsets of this cell and its axis-0/1 neighbours (-2,-1,+1,+2)
     const int o_c = plane_slot(tx, ty) * P;
     const int ox[4] = {plane_slot(tx - 2, ty) * P, plane_slot(tx - 1, ty) * P,
@@ -222,6 +225,12 @@ void k_march(
                             : (fsel == 3 ? rho[c] : (fsel == 4 ? kap_a[c] : (fsel == 5 ? kap_s[c] : T[c])));
         }
     };
+    // the cell's beam flag, prefetched one plane ahead with the fluid state
+    // (so the plane loop does not wait on a late load behind the next
+    // plane's prefetch) and kept as loaded until lane 7 stores it
+    auto load_beam = [&](int z) -> int {
+        return G.beam != nullptr ? (int)G.beam[(long long)z * pcells + row] : 0;
+    };
 
     // first plane of the segment into LDS: own cell from the queue, two halo
     // cells per lane group; later planes are written at the end of a step
@@ -241,6 +250,7 @@ void k_march(
         }
         const double flv = load_fluid(sg.z0);
         if (a < 7) s_fl[cl][a] = flv;
+        if (a == 7) s_beam[cl] = load_beam(sg.z0);
     }
     // Axis-2 face value carried from plane to plane.  The upper face of plane
     // z is the lower face of plane z+1, and both cells form its value with
@@ -296,17 +306,23 @@ void k_march(
         const bool more = z + 1 < sg.z1;
         Real qn[NC], hn[kHPG][NC];
         double fln = 0.0;
+        int bmn = 0;
+        // this plane's four-momentum bookkeeping of the cell (lanes 0..3),
+        // read before the prefetch so its wait does not include it
+        const long long cidx = (long long)z * pcells + row;
+        double dpre = 0.0;
+        if (dT0 && a < 4) dpre = dT0[4 * cidx + a];
         if (more) {
             load_row(z + 3, row, 0u, qn);
 #pragma unroll
             for (int j = 0; j < kHPG; ++j) load_row(z + 1, hrow[j], htest[j], hn[j]);
-            fln = load_fluid(z + 1);
+            fln = load_fluid(z + 1);   // lane 7 re-reads T, unused
+            bmn = load_beam(z + 1);
         }
         const bool lum_here = on_lum_xy || (G.lum_axis == 2 && z == (lside ? G.n2 - 1 : 0));
         const bool lum_wave = __ballot(lum_here) != 0;   // wave-uniform
 
         // ------------------------------------------------------ transport
-        const long long cidx = (long long)z * pcells + row;
         Real Is[NC];
         // Each feature flag is 0 (off), 1 (on) or 2 (tested at run time): the
         // common cases get straight-line code over the NC directions, which
@@ -451,7 +467,7 @@ void k_march(
         const double Tp2 = Tp * Tp;
         const double S = aa * G.a_rad * Tp2 * Tp2 + as * Ep;
         const Real cS = Real(dt * S / kFourPi);
-        const bool beam_cell = G.beam != nullptr && G.beam[cidx];
+        const bool beam_cell = s_beam[cl] != 0;
         Real *dst = Iout + cidx * N;
         Real Ipv[NC];
 #pragma unroll
@@ -485,12 +501,11 @@ void k_march(
             } else {
                 group_sum_v<SW, 4>(sm);
             }
-            if (a == 0) {
-#pragma unroll
-                for (int al = 0; al < 4; ++al)
-                    dT0[4 * cidx + al] -= (STG ? st.wS : 1.0) * n0u *
-                                          (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
-                                           E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
+            if (a < 4) {
+                const int al = a;
+                dT0[4 * cidx + al] = dpre - (STG ? st.wS : 1.0) * n0u *
+                                                (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
+                                                 E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
             }
         }
         // single buffer: every group must be done reading plane z first.
@@ -514,6 +529,7 @@ void k_march(
                 qz[4][k] = qn[k];
             }
             if (a < 7) s_fl[cl][a] = fln;
+            if (a == 7) s_beam[cl] = bmn;
         }
     }
 
@@ -548,14 +564,9 @@ int launch_one(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T
                double dt, double *dT0, Real *Istar, const Partials &P,
                const MStage<Real> &st = MStage<Real>{}) {
     const MarchInfo &M = g->march;
-    static bool lds_set = false;   // one attribute call per instantiation
-    if (!lds_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_march<Real, SW, NC, STG>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)M.lds) != hipSuccess)
-            return RT_EDEVICE;
-        lds_set = true;
-    }
+    if (ensure_dynamic_lds(reinterpret_cast<const void *>(&k_march<Real, SW, NC, STG>), M.lds) !=
+        RT_OK)
+        return RT_EDEVICE;
     hipLaunchKernelGGL((k_march<Real, SW, NC, STG>), dim3(M.grid), dim3(kTC * SW), M.lds, s,
                        g->dg, M, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho,
                        u, ka, ks, dt, dT0, P.sums, P.noroot, Istar, st);

@@ -11,7 +11,9 @@
 // results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <mutex>
+#include <utility>
 
 #include "k_transport.h"
 
@@ -549,6 +551,28 @@ int scratch_address(void **ptr, size_t *bytes) {
     }
     *ptr = g_scratch_addr[dev];
     *bytes = kScratchBytes;
+    return RT_OK;
+}
+
+// Dynamic-LDS limit of a kernel on the current device: raised once per
+// (device, kernel) to `bytes` (or more), under a lock, before its first
+// launch on that device.
+namespace {
+std::mutex g_lds_mu;
+std::map<std::pair<int, const void *>, int> g_lds_limit;
+}  // namespace
+
+int ensure_dynamic_lds(const void *kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return RT_OK;   // within the default limit
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RT_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_lds_mu);
+    int &cur = g_lds_limit[{dev, kernel}];
+    if (cur >= (int)bytes) return RT_OK;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+        hipSuccess)
+        return RT_EDEVICE;
+    cur = (int)bytes;
     return RT_OK;
 }
 

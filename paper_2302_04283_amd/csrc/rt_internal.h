@@ -127,6 +127,9 @@ int step_partial_blocks(const rt_grid *g);
 // device address of this device's static scratch (the calling thread's
 // current device); looked up once per device
 int scratch_address(void **ptr, size_t *bytes);
+// raise a kernel's dynamic-LDS limit on the current device to `bytes` (once
+// per device and kernel, thread-safe); a no-op within the default 64 KiB
+int ensure_dynamic_lds(const void *kernel, size_t bytes);
 bool march_config(int precision, int nang, int &sw, int &nc);
 size_t march_lds_bytes(int precision, int nang, int np);
 int march_pstride(int precision, int nang);
