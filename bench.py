@@ -43,6 +43,8 @@ FLOPS_FLAT = 69
 FLOPS_CURVED = 76
 KERNEL_SOURCES = {"k_march": ["k_march.hip", "k_tile.h", "k_common.h"],
                   "k_column": ["k_column.hip", "k_transport.h", "k_common.h"]}
+# rt_grid_info path codes
+KERNEL_NAMES = {0: "general", 1: "tiled", 2: "column"}
 
 
 def _upload_initial(prob, dtype, dev):
@@ -108,7 +110,7 @@ def time_path(prob, precision, steps, warmup, dt, dev):
     g = rt.Grid(prob, precision, dev.index or 0)
     print("[bench] %s %dx%dx%d x %d: %s kernel" % (
         "fp32" if precision == rt.RT_F32 else "fp64", prob.n[0], prob.n[1], prob.n[2], prob.nang,
-        {0: "general", 1: "tiled", 2: "column"}[g.path]), file=sys.stderr, flush=True)
+        KERNEL_NAMES[g.path]), file=sys.stderr, flush=True)
     Ia = _upload_initial(prob, g.real_dtype(), dev)
     Ib = torch.empty_like(Ia)
     T = torch.as_tensor(prob.T).to(dev)
@@ -132,6 +134,7 @@ def time_path(prob, precision, steps, warmup, dt, dev):
     wall = time.perf_counter() - t0
     per = [a.elapsed_time(b) * 1e-3 for a, b in evs]
     st = g.stats()
+    st["kernel"] = KERNEL_NAMES[g.path]
     g.close()
     del Ia, Ib
     torch.cuda.empty_cache()
@@ -419,11 +422,11 @@ def main():
                                             "traffic_k_column_c5.json")}
         if not args.no_fp64:
             n64 = max(2, n5 // 4)
-            w64, per64, _ = time_path(p5, rt.RT_F64, n64, 1, dt5, dev)
+            w64, per64, st64 = time_path(p5, rt.RT_F64, n64, 1, dt5, dev)
             print("[bench] torus fp64 done: %.2f ms/step" % (1e3 * w64 / n64), file=sys.stderr,
                   flush=True)
             t5["fp64"] = {"value": p5.ncell * p5.nang * n64 / w64, "ms_per_step": 1e3 * w64 / n64,
-                          "steps": n64, "kernel": "general",
+                          "steps": n64, "kernel": st64["kernel"],
                           "speedup_fp32_over_fp64": t5["fp32"]["value"] / (p5.ncell * p5.nang * n64 / w64)}
         if not args.no_adjoint:
             wfa, finite = time_fwd_adjoint(p5, rt.RT_F32, n5, 4, dt5, dev)
@@ -480,22 +483,22 @@ def main():
         p5l.latlong = (8, 16)
         w5l, _, _ = time_path(p5l, rt.RT_F32, 20, 2, dt, dev)
         out["latlong_8x16_fp32"] = {"value": ncell * 128 * 20 / w5l, "ms_per_step": 1e3 * w5l / 20}
-        # Kerr-Schild, 128 x 64 x 128 cells, 162 directions (column kernel in
-        # FP32, general in FP64), and with MAPR angular fluxes (general)
+        # Kerr-Schild, 128 x 64 x 128 cells, 162 directions (column kernel),
+        # and with MAPR angular fluxes (general kernel)
         p6 = W.make_problem("c3")
         g6 = rt.Grid(p6, rt.RT_F32, dev.index or 0)
         dt6 = g6.max_dt(p6.cfl)
         g6.close()
-        w6, _, _ = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
+        w6, _, st6 = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
         out["kerr_schild_128x64x128_fp32"] = {"value": p6.ncell * p6.nang * 10 / w6,
-                                              "ms_per_step": 1e3 * w6 / 10, "kernel": "column"}
-        w6d, _, _ = time_path(p6, rt.RT_F64, 10, 2, dt6, dev)
+                                              "ms_per_step": 1e3 * w6 / 10, "kernel": st6["kernel"]}
+        w6d, _, st6d = time_path(p6, rt.RT_F64, 10, 2, dt6, dev)
         out["kerr_schild_128x64x128_fp64"] = {"value": p6.ncell * p6.nang * 10 / w6d,
-                                              "ms_per_step": 1e3 * w6d / 10, "kernel": "general"}
+                                              "ms_per_step": 1e3 * w6d / 10, "kernel": st6d["kernel"]}
         p6.ang_recon = 2
-        w7, _, _ = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
+        w7, _, st7 = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
         out["kerr_schild_mapr_fp32"] = {"value": p6.ncell * p6.nang * 10 / w7,
-                                        "ms_per_step": 1e3 * w7 / 10, "kernel": "general"}
+                                        "ms_per_step": 1e3 * w7 / 10, "kernel": st7["kernel"]}
         print("[bench] context done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -570,7 +570,7 @@ int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
 
 // Segments of the column march: enough workgroups to fill the chip several
 // times over (about 32 wavefronts per CU), at least 4 planes per segment.
-bool column_config(rt_grid *g, int seglen_hint, bool force) {
+bool column_config(rt_grid *g, int seglen_hint) {
     ColumnInfo &CI = g->column;
     const DevGrid &G = g->dg;
     const long long cols = (long long)G.n0 * G.n1;
@@ -588,11 +588,12 @@ bool column_config(rt_grid *g, int seglen_hint, bool force) {
     CI.nwork = nwork;
     CI.grid = (int)((blocks + 7) / 8 * 8);
     const int real = g->precision == RT_F32 ? 4 : 8;
-    // direction chunks whose registers fit without spilling (col_waves); in
-    // FP64 from three chunks on the general kernel, at more resident waves,
-    // is faster (128 x 64 x 128 x 162 Kerr-Schild: 7.4 against 9.5 ms)
+    // up to six direction chunks in either precision (FP64 with five or six
+    // spills a few registers and is still faster than the general kernel:
+    // 256 x 128 x 256 x 362 Kerr-Schild 125 against 169 ms, 128 x 64 x 128 x
+    // 162 5.9 against 7.5 ms)
     const int nch = (G.nang + kWave - 1) / kWave;
-    if (nch > (real == 4 ? 6 : (force ? 4 : 2))) return false;
+    if (nch > 6) return false;
     CI.own_stride = (G.nang + 3) / 4 * 4;
     // direction tables: unit vectors and solid angles (FP64), edge records
     CI.tab_bytes = ((size_t)G.nang * (4 * sizeof(double) + kMaxNbr * sizeof(int)) + 15) / 16 * 16;

@@ -270,7 +270,7 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
         if (!g->march.enabled && d->kernel != 1 && d->geo_extent[2] == 1 && g->integrator == 1 &&
             !(d->tau_coeff > 0.0) && !d->rad_velocity && d->ang_recon == 0 &&
             (N + rt::kWave - 1) / rt::kWave <= rt::kMaxChunks)
-            g->column.enabled = rt::column_config(g, d->seglen, d->kernel == 2) ? 1 : 0;
+            g->column.enabled = rt::column_config(g, d->seglen) ? 1 : 0;
         // this device's static scratch for rt_step_noalloc (looked up once per
         // device, with the device current); a failed lookup leaves it unset and
         // only that entry point reports it

@@ -154,7 +154,7 @@ int launch_adj_march(rt_grid *g, hipStream_t s, const void *Iin, const void *psi
 int launch_adj_column(rt_grid *g, hipStream_t s, const void *Iin, const void *psi, double dt,
                       double lum_weight, void *lamI0);
 // k_column.hip
-bool column_config(rt_grid *g, int seglen_hint, bool force);
+bool column_config(rt_grid *g, int seglen_hint);
 int launch_column(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                   const double *rho, const double *u, const double *ka, const double *ks,
                   double dt, double *dT0, void *Istar, const Partials &P);

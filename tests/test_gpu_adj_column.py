@@ -78,9 +78,6 @@ def _cases():
 @pytest.mark.parametrize("name,prob", _cases(), ids=[c[0] for c in _cases()])
 def test_column_adjoint_equals_general_adjoint(name, prob, prec, use_istar):
     p = prob
-    nch = (p.nang + 63) // 64
-    if prec == rt.RT_F64 and nch > 4:
-        pytest.skip("FP64 with %d direction chunks: no column path" % nch)
     g = rt.Grid(p, prec)
     dt = g.max_dt(p.cfl)
     g.close()

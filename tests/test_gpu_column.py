@@ -67,11 +67,8 @@ def test_column_kernel_equals_general_kernel(name, prob, prec):
     dt = g.max_dt(p.cfl)
     auto = g.path
     g.close()
-    nch = (p.nang + 63) // 64
-    # the automatic choice: the column kernel in FP32 and up to two FP64 chunks
-    assert auto == (2 if (prec == rt.RT_F32 or nch <= 2) else 0), (name, auto)
-    if prec == rt.RT_F64 and nch > 4:
-        pytest.skip("FP64 with %d direction chunks: the column kernel would spill" % nch)
+    # the automatic choice: the column kernel in both precisions
+    assert auto == 2, (name, auto)
     print("[column] %s %s n=%s nang=%d" % (name, "fp64" if prec == rt.RT_F64 else "fp32",
                                            p.n, p.nang), flush=True)
     a = _run(p, prec, 3, dt, 2)
