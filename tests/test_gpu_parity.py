@@ -266,3 +266,42 @@ def test_general_kernel_forced_matches_oracle():
     assert not g.fast_path
     g.close()
     _compare(p, rt.RT_F64, 3, F64_I, F64_T, "general kernel forced, 8^3 fp64")
+
+
+# The FP32 gas temperature sits at the floor FP32 storage of the intensities
+# sets: each stored intensity carries a relative rounding of u = 2^-24, the
+# N independent roundings reach the radiation energy E = sum I dOmega as
+# about u E / sqrt(N), and energy conservation hands that to the gas, so a
+# cell's temperature error per step is about u kappa / sqrt(N) with
+# kappa = E / (rho c_v T) the condition number of T in E.  The test asserts
+# that every cell's FP32 temperature error is within a small multiple of its
+# own floor (per step taken), which is the claim that no other FP32 error
+# source reaches the gas temperature.
+FLOOR_U = 2.0 ** -24
+
+
+@pytest.mark.parametrize("cfg,scale,steps", [("c1", None, 10), ("c2", (16, 16, 16), 6),
+                                             ("c3", (16, 12, 8), 4)])
+def test_fp32_gas_temperature_error_sits_at_the_storage_floor(cfg, scale, steps):
+    p = W.make_problem(cfg, scale=scale) if scale else W.make_problem(cfg)
+    S = O.setup(p)
+    dt = O.max_dt(S, p.cfl)
+    Io, To, _, _, _ = oracle_run(p, steps, dt)
+    Ig, Tg, _, _, g = gpu_run(p, rt.RT_F32, steps, dt)
+    g.close()
+    N = Io.shape[-1]
+    cv = p.kb_mu_mp / (p.gamma_gas - 1.0)
+    E0 = (np.asarray(p.initial_intensity()) * S.domega.numpy()).sum(-1)
+    E1 = (Io * S.domega.numpy()).sum(-1)
+    # the larger of the condition numbers at the start and at the end
+    kappa = np.maximum(E0 / (p.rho * cv * p.T), E1 / (p.rho * cv * To))
+    floor = FLOOR_U * kappa / math.sqrt(N)
+    eT = np.abs(Tg - To) / To
+    ratio = eT / (floor + 1e-300)
+    worst = float(ratio.max())
+    _report("%s fp32 gas-temperature floor %d steps" % (cfg, steps), e_T=float(eT.max()),
+            floor_max=float(floor.max()), ratio_max=worst, ratio_median=float(np.median(ratio)))
+    # within a few floors per step taken, plus FP64 rounding of T itself
+    # (measured worst cells: c1 1.0 floors over 10 steps, c2 19 over 6 -- the
+    # beam cells --, c3 5.0 over 4)
+    assert np.all(eT <= 6.0 * steps * floor + 1e-14), worst
