@@ -115,6 +115,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
     for (int k = threadIdx.x; k < 3 * N; k += kColBlock) s_nhat[k] = G.nhat[k];
     for (int k = threadIdx.x; k < N; k += kColBlock) s_dom[k] = G.domega[k];
+    __shared__ double s_E0[kColWaves][16];   // E0 of each wave's column
 
     // XCD-aware logical block: the hardware hands block b to XCD b % 8
     const int per = gridDim.x / 8;
@@ -153,6 +154,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     const Real ivol = static_cast<const Real *>(G.invV)[x.gc];
     const double volD = G.volD[x.gc];
     const double n0 = G.n0u[x.gc];
+    if (lane < 16) s_E0[wave][lane] = G.E0[16 * x.gc + lane];
     const bool plm = G.recon == RT_RECON_PLM;
     const Real dtR = Real(dt);
 
@@ -273,6 +275,25 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 }
             }
         };
+        // FP32 with six chunks (no DMA buffers: they would leave one
+        // workgroup per CU): the next plane's eight neighbour rows are
+        // prefetched into registers instead, as loaded (the vacuum-ghost
+        // zeros applied where they are used); two waves per SIMD leave the
+        // registers for it
+        constexpr bool RPF = !DMA && sizeof(Real) == 4 && NCH == 6;
+        auto load_rows_raw = [&](int pz, Real (&dst)[8][NCH]) {
+            const Real *base = Iin + (long long)pz * pcells * N;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool need = plm || (k % 4 == 1) || (k % 4 == 2);
+                const Real *src = base + (long long)ncol[k] * N;
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int n = lane + kWave * ch;
+                    dst[k][ch] = need ? src[ch < NCH - 1 ? n : min(n, N - 1)] : Real(0);
+                }
+            }
+        };
         // the eight neighbour rows of plane pz straight into this wave's LDS
         // buffer: each lane moves one value per (row, chunk); the last chunk's
         // lanes past the row re-read its last entry (never used)
@@ -296,6 +317,8 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
         };
         const int mycol = (int)x.c;
         if constexpr (DMA) dma_rows(z0);
+        Real pnb[RPF ? 8 : 1][NCH];
+        if constexpr (RPF) load_rows_raw(z0, pnb);
         // planes z-1 .. z+2 of the column; the lower axis-2 face flux of the
         // segment's first plane is formed here (it also needs plane z0-2)
         Real qz[4][NCH];
@@ -325,6 +348,11 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 // own loads: vmcnt reaches zero)
                 __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             }
+            // this plane's bookkeeping row (lanes 0..3) and beam flag, read
+            // before the prefetches are issued so their waits do not include them
+            double dpre = 0.0;
+            if (dT0 && lane < 4) dpre = dT0[4 * c + lane];
+            const int bflag = G.beam != nullptr ? (int)G.beam[c] : 0;
             // the column's next plane while this one is computed
             Real qn[NCH];
             unsigned qneed = 0;
@@ -357,6 +385,14 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                             nb[kk][ch] = (fl[ch] & (1u << (kGhostShift + k))) ? Real(0) : v;
                         }
                     }
+                } else if constexpr (RPF) {
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int k = 4 * a + kk;
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch)
+                            nb[kk][ch] = (fl[ch] & (1u << (kGhostShift + k))) ? Real(0) : pnb[k][ch];
+                    }
                 } else {
                     load_axis(z, a, nb);
                 }
@@ -383,6 +419,9 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
                     dma_rows(z + 1);
                 }
+            }
+            if constexpr (RPF) {
+                if (more) load_rows_raw(z + 1, pnb);
             }
             Real Is[NCH];
 #pragma unroll
@@ -456,7 +495,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             const double S = aa * G.a_rad * Tp2 * Tp2 + as * Ep;
             const double cS = S * (dt / kFourPi);
             double sm[4] = {0.0, 0.0, 0.0, 0.0};
-            const bool beam_cell = G.beam != nullptr && G.beam[c];
+            const bool beam_cell = bflag != 0;
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const int n = lane + kWave * ch;
@@ -484,12 +523,11 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             }
             if (dT0) {
                 wave_sum_quads(sm);
-                if (lane == 0) {
-                    const double *E0 = G.E0 + 16 * x.gc;
-#pragma unroll
-                    for (int al = 0; al < 4; ++al)
-                        dT0[4 * c + al] -= n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
-                                                 E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
+                if (lane < 4) {
+                    const double *E0 = s_E0[wave];
+                    const int al = lane;
+                    dT0[4 * c + al] = dpre - n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
+                                                   E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
                 }
             }
             if (more) {
