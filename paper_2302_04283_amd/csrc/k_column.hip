@@ -17,12 +17,11 @@
 //     of a plane is carried to the next plane, so the plane below is not
 //     needed;
 //   * axis-0/1 neighbour rows (two columns each way for PLM): with FP32
-//     intensities and up to three direction chunks the next plane's rows go
-//     straight from HBM/L2 into a per-wave LDS buffer (global_load_lds) as
+//     intensities the next plane's eight rows are loaded into registers as
 //     soon as the current plane's transport has read them, so their latency
-//     hides behind the angular fluxes and the coupling without holding
-//     registers; otherwise they are loaded into registers one axis at a
-//     time;
+//     hides behind the angular fluxes and the coupling (except at four
+//     chunks, where those registers would cost a resident wave); otherwise
+//     they are loaded one axis at a time;
 //   * the cell's own row is staged in LDS for the angular-edge gather;
 //   * workgroups are dispatched round-robin over the 8 XCDs; the logical
 //     order gives each XCD a contiguous band of columns, so neighbour
@@ -84,9 +83,8 @@ __device__ __forceinline__ void axis_faces(const Real (&v)[5], bool plm, unsigne
     uhi = hi_p ? v[2] + hl0 : (hi_n ? v[3] - hlp : Real(0));
 }
 
-// VWLDS: the column's edge weights staged in LDS; DMA: axis-0/1 neighbour
-// rows prefetched into LDS (FP32)
-template <typename Real, int NCH, bool VWLDS, bool DMA>
+// VWLDS: the column's edge weights staged in LDS (FP32)
+template <typename Real, int NCH, bool VWLDS>
 __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_waves<Real, NCH>()))) void k_column(
     DevGrid G, ColumnInfo CI, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
@@ -102,16 +100,15 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     extern __shared__ __align__(16) unsigned char s_dyn[];
     // the direction tables every plane reads -- unit vectors, solid angles,
     // angular-edge records -- staged once per workgroup, so the plane loop
-    // issues no global load behind the neighbour-row DMA (vector-memory
+    // issues no global load behind the neighbour-row prefetch (vector-memory
     // counters retire in order: a later load's wait would also wait for it)
     double *s_nhat = reinterpret_cast<double *>(s_dyn);     // [N][3]
     double *s_dom = s_nhat + 3 * N;                          // [N]
     int *s_adj = reinterpret_cast<int *>(s_dom + N);         // [N][6]
     // per wave: the cell's row [own_stride], the column's edge weights [2E]
-    // (VWLDS), the next plane's eight neighbour rows [8][NCH][64] (DMA)
+    // (VWLDS)
     Real *s_own = reinterpret_cast<Real *>(s_dyn + CI.tab_bytes) + (size_t)wave * CI.wave_lds;
     Real *s_vw = s_own + CI.own_stride;
-    Real *s_nb = s_vw + (VWLDS ? 2 * E : 0);
     for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
     for (int k = threadIdx.x; k < 3 * N; k += kColBlock) s_nhat[k] = G.nhat[k];
     for (int k = threadIdx.x; k < N; k += kColBlock) s_dom[k] = G.domega[k];
@@ -275,12 +272,14 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 }
             }
         };
-        // FP32 with six chunks (no DMA buffers: they would leave one
-        // workgroup per CU): the next plane's eight neighbour rows are
-        // prefetched into registers instead, as loaded (the vacuum-ghost
-        // zeros applied where they are used); two waves per SIMD leave the
-        // registers for it
-        constexpr bool RPF = !DMA && sizeof(Real) == 4 && NCH == 6;
+        // FP32: the next plane's eight neighbour rows are prefetched into
+        // registers, as loaded (the vacuum-ghost zeros applied where they are
+        // used), where that costs no resident wave: up to three chunks stay
+        // at three waves per SIMD, five and six at two (at four the rows
+        // would take the third wave away).  Faster than moving them into LDS
+        // by global_load_lds (128 x 64 x 128 x 162: 3.17 against 3.27 ms),
+        // which at six chunks would also leave one workgroup per CU.
+        constexpr bool RPF = sizeof(Real) == 4 && NCH != 4;
         auto load_rows_raw = [&](int pz, Real (&dst)[8][NCH]) {
             const Real *base = Iin + (long long)pz * pcells * N;
 #pragma unroll
@@ -294,29 +293,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 }
             }
         };
-        // the eight neighbour rows of plane pz straight into this wave's LDS
-        // buffer: each lane moves one value per (row, chunk); the last chunk's
-        // lanes past the row re-read its last entry (never used)
-        auto dma_rows = [&](int pz) {
-            if constexpr (DMA) {
-                const Real *base = Iin + (long long)pz * pcells * N;
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    if (!plm && (k % 4 == 0 || k % 4 == 3)) continue;
-                    const Real *src = base + (long long)ncol[k] * N;
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch) {
-                        const int n = lane + kWave * ch;
-                        __builtin_amdgcn_global_load_lds(
-                            src + (ch < NCH - 1 ? n : min(n, N - 1)),
-                            (__attribute__((address_space(3))) void *)(s_nb + (k * NCH + ch) * kWave),
-                            4, 0, 0);
-                    }
-                }
-            }
-        };
         const int mycol = (int)x.c;
-        if constexpr (DMA) dma_rows(z0);
         Real pnb[RPF ? 8 : 1][NCH];
         if constexpr (RPF) load_rows_raw(z0, pnb);
         // planes z-1 .. z+2 of the column; the lower axis-2 face flux of the
@@ -343,11 +320,6 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
         for (int z = z0; z < z1; ++z) {
             const long long c = (long long)z * pcells + x.c;
             const bool more = z + 1 < z1;
-            if constexpr (DMA) {
-                // this plane's neighbour rows have landed in LDS (the wave's
-                // own loads: vmcnt reaches zero)
-                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-            }
             // this plane's bookkeeping row (lanes 0..3) and beam flag, read
             // before the prefetches are issued so their waits do not include them
             double dpre = 0.0;
@@ -374,18 +346,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 Real nb[4][NCH];
-                if constexpr (DMA) {
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const int k = 4 * a + kk;
-                        const bool need = plm || kk == 1 || kk == 2;
-#pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch) {
-                            const Real v = need ? s_nb[(k * NCH + ch) * kWave + lane] : Real(0);
-                            nb[kk][ch] = (fl[ch] & (1u << (kGhostShift + k))) ? Real(0) : v;
-                        }
-                    }
-                } else if constexpr (RPF) {
+                if constexpr (RPF) {
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
                         const int k = 4 * a + kk;
@@ -410,14 +371,6 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     if (lum_here && G.lum_axis == a && n < N)
                         lum_acc += G.lum_side ? -s_dom[n] * (double)Fhi : s_dom[n] * (double)Flo;
                     dq[ch] += Fhi - Flo;
-                }
-            }
-            if constexpr (DMA) {
-                if (more) {
-                    // every LDS read of this plane's rows has returned before
-                    // the next plane's rows are written over them
-                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
-                    dma_rows(z + 1);
                 }
             }
             if constexpr (RPF) {
@@ -576,13 +529,10 @@ int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
     const DevGrid &G = g->dg;
     const size_t lds = CI.tab_bytes + (size_t)kColWaves * CI.wave_lds * sizeof(Real);
     const int nch = (G.nang + kWave - 1) / kWave;
-    // FP32: edge weights in LDS; neighbour rows by LDS DMA up to three chunks
-    // (beyond, the buffers of four waves would leave one workgroup per CU:
-    // 256 x 128 x 256 x 362 ran 118 ms with them, 101 ms without)
+    // FP32: edge weights in LDS
 #define RT_COL(NC)                                                                             \
     case NC:                                                                                   \
-        hipLaunchKernelGGL((k_column<Real, NC, sizeof(Real) == 4,                              \
-                                     sizeof(Real) == 4 && NC <= 3>),                           \
+        hipLaunchKernelGGL((k_column<Real, NC, sizeof(Real) == 4>),                            \
                            dim3(CI.grid), dim3(kColBlock), lds, s,                             \
                            G, CI, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, \
                            rho, u, ka, ks, dt, dT0, P.sums, P.noroot,                          \
@@ -595,8 +545,6 @@ int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
         RT_COL(4)
         RT_COL(5)
         RT_COL(6)
-        RT_COL(7)
-        RT_COL(8)
         default:
             return RT_EINVAL;
     }
@@ -635,10 +583,8 @@ bool column_config(rt_grid *g, int seglen_hint) {
     CI.own_stride = (G.nang + 3) / 4 * 4;
     // direction tables: unit vectors and solid angles (FP64), edge records
     CI.tab_bytes = ((size_t)G.nang * (4 * sizeof(double) + kMaxNbr * sizeof(int)) + 15) / 16 * 16;
-    // as the launcher instantiates: FP32 edge weights in LDS, FP32
-    // neighbour-row buffer [8][nch][64] up to three chunks
-    CI.wave_lds = CI.own_stride + (real == 4 ? 2 * G.nedge : 0) +
-                  (real == 4 && nch <= 3 ? 8 * nch * kWave : 0);
+    // as the launcher instantiates: FP32 edge weights in LDS
+    CI.wave_lds = CI.own_stride + (real == 4 ? 2 * G.nedge : 0);
     // within the default dynamic LDS limit (no attribute call needed)
     return CI.tab_bytes + (size_t)kColWaves * CI.wave_lds * real <= 64 * 1024;
 }
