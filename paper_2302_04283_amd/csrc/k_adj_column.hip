@@ -11,10 +11,9 @@
 // the same order, so both kernels give bit-identical results.
 //
 // Mapping (gfx950): one 64-lane wavefront marches one column segment along
-// axis 2 for a slice of the directions (the transport adjoint has no sums
-// over directions, so a row of up to six 64-direction chunks splits over
-// waves: up to three chunks per wave in FP32, one in FP64; the waves of one
-// column run in neighbouring workgroups, so they share its rows in L2).
+// axis 2 for one 64-direction chunk (the transport adjoint has no sums over
+// directions, so a row of up to six chunks splits over waves; the waves of
+// one column run in neighbouring workgroups, so they share its rows in L2).
 //   * the column's geometry per direction -- q, the eight axis-0/1 face
 //     coefficients (faces i-1 .. i+2 and j-1 .. j+2), the axis-2
 //     coefficient, packed face/ghost/mask flags -- is loaded once per
@@ -547,27 +546,20 @@ template <typename Real>
 int launch_acol_t(rt_grid *g, hipStream_t s, const void *Iin, const void *psi, double dt,
                   double lum_weight, void *lam) {
     const int nch = (g->dg.nang + kWave - 1) / kWave;
-    // direction chunks per wave: up to three in FP32 (neighbour rows by DMA),
-    // one in FP64 (registers for two resident waves per SIMD)
-    const int cmax = sizeof(Real) == 4 ? 3 : 1;
+    // one direction chunk per wave: the fewest registers (FP32 90 VGPRs,
+    // against 160 with two chunks and 197 with three) and the most resident
+    // waves outweigh the per-wave work repeated for each chunk (the plane
+    // flags, the column's full psi row): 256 x 128 x 256 x 362 adjoint step
+    // 81.9 ms against 93.6 (two) and 86.5 (three)
+    const int cmax = 1;
     const int nsplit = (nch + cmax - 1) / cmax;
     const int ncw = (nch + nsplit - 1) / nsplit;
     const Real *in = static_cast<const Real *>(Iin);
     const Real *ps = static_cast<const Real *>(psi);
     Real *out = static_cast<Real *>(lam);
     constexpr bool dma = sizeof(Real) == 4;
-    switch (ncw) {
-        case 1: return launch_acol<Real, 1, dma>(g, s, in, ps, dt, lum_weight, out, nsplit);
-        case 2:
-            if constexpr (sizeof(Real) == 4)
-                return launch_acol<Real, 2, dma>(g, s, in, ps, dt, lum_weight, out, nsplit);
-            return RT_EINVAL;
-        case 3:
-            if constexpr (sizeof(Real) == 4)
-                return launch_acol<Real, 3, dma>(g, s, in, ps, dt, lum_weight, out, nsplit);
-            return RT_EINVAL;
-        default: return RT_EINVAL;
-    }
+    if (ncw != 1) return RT_EINVAL;
+    return launch_acol<Real, 1, dma>(g, s, in, ps, dt, lum_weight, out, nsplit);
 }
 
 }  // namespace
