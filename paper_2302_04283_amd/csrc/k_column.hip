@@ -83,8 +83,12 @@ __device__ __forceinline__ void axis_faces(const Real (&v)[5], bool plm, unsigne
     uhi = hi_p ? v[2] + hl0 : (hi_n ? v[3] - hlp : Real(0));
 }
 
-// VWLDS: the column's edge weights staged in LDS (FP32)
-template <typename Real, int NCH, bool VWLDS>
+// VWLDS: the column's edge weights staged in LDS (FP32).  SPL: waves per
+// column; with SPL = 2 the column's direction chunks split over two waves
+// (NCH each) of the same workgroup, which share the cell's row through LDS
+// and add their partial FP64 angle sums there (half 0's first); both then
+// solve the same quartic
+template <typename Real, int NCH, bool VWLDS, int SPL>
 __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_waves<Real, NCH>()))) void k_column(
     DevGrid G, ColumnInfo CI, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
@@ -95,6 +99,8 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     // wave-uniform (scalar registers): the column and every row address
     // derived from it
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int wc = wave / SPL, hh = wave % SPL;   // column slot, half
+    const int lbase = lane + kWave * NCH * hh;   // this wave's first direction
     const int N = G.nang;
     const int E = G.nedge;
     extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -105,10 +111,11 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     double *s_nhat = reinterpret_cast<double *>(s_dyn);     // [N][3]
     double *s_dom = s_nhat + 3 * N;                          // [N]
     int *s_adj = reinterpret_cast<int *>(s_dom + N);         // [N][6]
-    // per wave: the cell's row [own_stride], the column's edge weights [2E]
-    // (VWLDS)
-    Real *s_own = reinterpret_cast<Real *>(s_dyn + CI.tab_bytes) + (size_t)wave * CI.wave_lds;
-    Real *s_vw = s_own + CI.own_stride;
+    // per column: the cell's row, double-buffered [2][own_stride], the
+    // column's edge weights [2E] (VWLDS)
+    Real *s_row = reinterpret_cast<Real *>(s_dyn + CI.tab_bytes) + (size_t)wc * CI.col_lds;
+    Real *s_vw = s_row + 2 * CI.own_stride;
+    __shared__ double s_x[kColWaves][8];   // partial angle sums of each wave (SPL = 2)
     for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
     for (int k = threadIdx.x; k < 3 * N; k += kColBlock) s_nhat[k] = G.nhat[k];
     for (int k = threadIdx.x; k < N; k += kColBlock) s_dom[k] = G.domega[k];
@@ -123,7 +130,8 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     // a band's height later, the axis-0 neighbours) of a column march at
     // the same time and its neighbour rows are read from L2
     const long long pcells = (long long)G.n0 * G.n1;
-    const int nq = (G.n0 + kColWaves - 1) / kColWaves;
+    constexpr int kCols = kColWaves / SPL;   // columns per workgroup
+    const int nq = (G.n0 + kCols - 1) / kCols;
     const long long per_seg = (long long)nq * G.n1;
     const int seg = (int)(logical / per_seg);
     const int r = (int)(logical % per_seg);
@@ -131,11 +139,19 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     const int band = min(r / (nq * kColBand), nband - 1);
     const int h = min(kColBand, G.n1 - band * kColBand);   // rows of this band
     const int t = r - band * nq * kColBand;
-    int i = (t / h) * kColWaves + wave, j = band * kColBand + t % h, z0 = 0, z1 = 0;
-    const bool active = seg < CI.nseg && i < G.n0;
+    int i = (t / h) * kCols + wc, j = band * kColBand + t % h, z0 = 0, z1 = 0;
+    // `active`: the wave marches (with SPL = 2 every wave of a workgroup with
+    // work does, since the halves meet at barriers every plane; a column past
+    // the grid's edge then marches the edge column and writes nothing);
+    // `writes`: its results are stored
+    const bool wg_on = seg < CI.nseg;
+    const bool col_ok = i < G.n0;
+    const bool active = SPL == 1 ? (wg_on && col_ok) : wg_on;
+    const bool writes = wg_on && col_ok;
     if (active) {
         z0 = seg * CI.seglen;
         z1 = min(G.n2, z0 + CI.seglen);
+        i = min(i, G.n0 - 1);
     } else {
         i = 0;
         j = 0;
@@ -185,7 +201,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     unsigned fl[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
-        const int n = lane + kWave * ch;
+        const int n = lbase + kWave * ch;
         const int m = n < N ? n : 0;
         const Real *C0 = static_cast<const Real *>(G.C[0]);
         const Real *C1 = static_cast<const Real *>(G.C[1]);
@@ -213,7 +229,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
         }
         fl[ch] = f;
     }
-    if (VWLDS && active) {
+    if (VWLDS && active && hh == 0) {
         const Real *row = vw + (size_t)x.gc * E * 2;
         for (int k = lane; k < 2 * E; k += kWave) s_vw[k] = row[k];
     }
@@ -243,7 +259,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             const Real *src = Iin + (zz * pcells + col) * N;
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                const int n = lane + kWave * ch;
+                const int n = lbase + kWave * ch;
                 dst[ch] = src[ch < NCH - 1 ? n : min(n, N - 1)];
             }
             return need;
@@ -266,7 +282,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 const Real *src = base + (long long)ncol[k] * N;
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
-                    const int n = lane + kWave * ch;
+                    const int n = lbase + kWave * ch;
                     const Real v = need ? src[ch < NCH - 1 ? n : min(n, N - 1)] : Real(0);
                     dst[kk][ch] = (fl[ch] & (1u << (kGhostShift + k))) ? Real(0) : v;
                 }
@@ -288,7 +304,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 const Real *src = base + (long long)ncol[k] * N;
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
-                    const int n = lane + kWave * ch;
+                    const int n = lbase + kWave * ch;
                     dst[k][ch] = need ? src[ch < NCH - 1 ? n : min(n, N - 1)] : Real(0);
                 }
             }
@@ -329,14 +345,18 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             Real qn[NCH];
             unsigned qneed = 0;
             if (more) qneed = load_raw(z + 3, mycol, qn);
-            // the cell's row into LDS for the angular gather
-            col_wave_sync();
+            // the cell's row into LDS for the angular gather (double-buffered:
+            // the other buffer's readers finished during the previous plane)
+            Real *s_own = s_row + ((z - z0) & 1) * CI.own_stride;
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                const int n = lane + kWave * ch;
+                const int n = lbase + kWave * ch;
                 if (n < N) s_own[n] = qz[1][ch];
             }
-            col_wave_sync();
+            if constexpr (SPL == 1)
+                col_wave_sync();
+            else
+                __syncthreads();
             const bool lum_here = lum_col || (G.lum_axis == 2 && z == (G.lum_side ? G.n2 - 1 : 0));
             // ------------------------------------------------------ transport
             // axis by axis (one axis's neighbour rows live at a time)
@@ -361,7 +381,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 const unsigned hp = a ? kSyhP : kSxhP, hn = a ? kSyhN : kSxhN;
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
-                    const int n = lane + kWave * ch;
+                    const int n = lbase + kWave * ch;
                     const unsigned f = fl[ch];
                     const Real v[5] = {nb[0][ch], nb[1][ch], qz[1][ch], nb[2][ch], nb[3][ch]};
                     Real ulo, uhi;
@@ -379,7 +399,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             Real Is[NCH];
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                const int n = lane + kWave * ch;
+                const int n = lbase + kWave * ch;
                 const unsigned f = fl[ch];
                 const Real Ic = qz[1][ch];
                 {
@@ -404,10 +424,10 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 }
                 Is[ch] = quot(Qs, qn_);
             }
-            if (Istar) {
+            if (Istar && writes) {
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
-                    const int n = lane + kWave * ch;
+                    const int n = lbase + kWave * ch;
                     if (n < N) Istar[c * N + n] = Is[ch];
                 }
             }
@@ -422,7 +442,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             double sf[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                const int n = lane + kWave * ch;
+                const int n = lbase + kWave * ch;
                 const int m = n < N ? n : 0;
                 const double nbr_ = u0 - fma(u1, s_nhat[3 * m], fma(u2, s_nhat[3 * m + 1], u3 * s_nhat[3 * m + 2]));
                 const double nb2 = nbr_ * nbr_;
@@ -437,6 +457,16 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 sf[2] = fma(dom, nbr_ * rr, sf[2]);
             }
             wave_sum_quads(sf);
+            if constexpr (SPL == 2) {
+                if (lane == 0) {
+                    s_x[wave][0] = sf[0];
+                    s_x[wave][1] = sf[1];
+                    s_x[wave][2] = sf[2];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sf[k] = s_x[wc * SPL][k] + s_x[wc * SPL + 1][k];
+            }
             const double Em = sf[0], A1 = sf[1], A2 = sf[2] * (dt / kFourPi);
             const double B4 = A2 * aa * G.a_rad;
             const double B1 = rh * G.cv * (1.0 - A2 * as);
@@ -451,7 +481,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             const bool beam_cell = bflag != 0;
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                const int n = lane + kWave * ch;
+                const int n = lbase + kWave * ch;
                 if (n >= N) continue;
                 Real out = Real(0);
                 if (!(fl[ch] & kMsk)) {
@@ -468,15 +498,24 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     out = Real(Ip);
                 }
                 if (beam_cell && n == G.beam_angle) out = Real(G.beam_I);
-                Iout[c * N + n] = out;
+                if (writes) Iout[c * N + n] = out;
             }
-            if (lane == 0) {
+            if (lane == 0 && hh == 0 && writes) {
                 T[c] = Tp;
                 nr_acc += bad;
             }
             if (dT0) {
                 wave_sum_quads(sm);
-                if (lane < 4) {
+                if constexpr (SPL == 2) {
+                    if (lane == 0) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) s_x[wave][4 + k] = sm[k];
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) sm[k] = s_x[wc * SPL][4 + k] + s_x[wc * SPL + 1][4 + k];
+                }
+                if (lane < 4 && hh == 0 && writes) {
                     const double *E0 = s_E0[wave];
                     const int al = lane;
                     dT0[4 * c + al] = dpre - n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
@@ -496,6 +535,11 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
         }
     }
     // -------------------------------------------------------- block partials
+    if (!writes) {
+        lum_acc = 0.0;
+        me_acc = 0.0;
+        nr_acc = 0;
+    }
     __shared__ double sh_l[kColWaves], sh_m[kColWaves];
     __shared__ int sh_n[kColWaves];
     lum_acc = group_sum<kWave>(lum_acc);
@@ -527,12 +571,23 @@ int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
                     double dt, double *dT0, void *Istar, const Partials &P) {
     const ColumnInfo &CI = g->column;
     const DevGrid &G = g->dg;
-    const size_t lds = CI.tab_bytes + (size_t)kColWaves * CI.wave_lds * sizeof(Real);
+    const size_t lds = CI.tab_bytes + (size_t)(kColWaves / CI.split) * CI.col_lds * sizeof(Real);
     const int nch = (G.nang + kWave - 1) / kWave;
-    // FP32: edge weights in LDS
+    // FP32: edge weights in LDS; six chunks split over two waves
+    if constexpr (sizeof(Real) == 4) {
+        if (CI.split == 2) {
+            if (nch != 6) return RT_EINVAL;
+            hipLaunchKernelGGL((k_column<Real, 3, true, 2>), dim3(CI.grid), dim3(kColBlock), lds, s,
+                               G, CI, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T,
+                               rho, u, ka, ks, dt, dT0, P.sums, P.noroot,
+                               static_cast<Real *>(Istar));
+            return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
+        }
+    }
+    if (CI.split != 1) return RT_EINVAL;
 #define RT_COL(NC)                                                                             \
     case NC:                                                                                   \
-        hipLaunchKernelGGL((k_column<Real, NC, sizeof(Real) == 4>),                            \
+        hipLaunchKernelGGL((k_column<Real, NC, sizeof(Real) == 4, 1>),                         \
                            dim3(CI.grid), dim3(kColBlock), lds, s,                             \
                            G, CI, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, \
                            rho, u, ka, ks, dt, dT0, P.sums, P.noroot,                          \
@@ -565,14 +620,6 @@ bool column_config(rt_grid *g, int seglen_hint) {
     seglen = std::min<long long>(seglen, G.n2);
     const long long nseg = (G.n2 + seglen - 1) / seglen;
     const long long nwork = cols * nseg;
-    // one workgroup per quad of columns along axis 0 (the last quad of a row
-    // may be partly idle) per row and segment
-    const long long blocks = (long long)((G.n0 + kColWaves - 1) / kColWaves) * G.n1 * nseg;
-    if (blocks >= (1LL << 30)) return false;
-    CI.seglen = (int)seglen;
-    CI.nseg = (int)nseg;
-    CI.nwork = nwork;
-    CI.grid = (int)((blocks + 7) / 8 * 8);
     const int real = g->precision == RT_F32 ? 4 : 8;
     // up to six direction chunks in either precision (FP64 with five or six
     // spills a few registers and is still faster than the general kernel:
@@ -580,13 +627,26 @@ bool column_config(rt_grid *g, int seglen_hint) {
     // 162 5.9 against 7.5 ms)
     const int nch = (G.nang + kWave - 1) / kWave;
     if (nch > 6) return false;
+    // FP32 with six chunks: two waves per column (three chunks each, three
+    // resident waves per SIMD instead of two)
+    CI.split = (real == 4 && nch == 6) ? 2 : 1;
+    // one workgroup per quad (pair, when split) of columns along axis 0 (the
+    // last of a row may be partly idle) per row and segment
+    const int cols_wg = kColWaves / CI.split;
+    const long long blocks = (long long)((G.n0 + cols_wg - 1) / cols_wg) * G.n1 * nseg;
+    if (blocks >= (1LL << 30)) return false;
+    CI.seglen = (int)seglen;
+    CI.nseg = (int)nseg;
+    CI.nwork = nwork;
+    CI.grid = (int)((blocks + 7) / 8 * 8);
     CI.own_stride = (G.nang + 3) / 4 * 4;
     // direction tables: unit vectors and solid angles (FP64), edge records
     CI.tab_bytes = ((size_t)G.nang * (4 * sizeof(double) + kMaxNbr * sizeof(int)) + 15) / 16 * 16;
-    // as the launcher instantiates: FP32 edge weights in LDS
-    CI.wave_lds = CI.own_stride + (real == 4 ? 2 * G.nedge : 0);
+    // per column, as the launcher instantiates: the cell's row twice, FP32
+    // edge weights
+    CI.col_lds = 2 * CI.own_stride + (real == 4 ? 2 * G.nedge : 0);
     // within the default dynamic LDS limit (no attribute call needed)
-    return CI.tab_bytes + (size_t)kColWaves * CI.wave_lds * real <= 64 * 1024;
+    return CI.tab_bytes + (size_t)cols_wg * CI.col_lds * real <= 64 * 1024;
 }
 
 int launch_column(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,

@@ -82,8 +82,9 @@ struct ColumnInfo {
     int enabled;
     int seglen, nseg, grid;
     long long nwork;              // column segments (one wavefront each)
-    int own_stride;               // LDS entries of a wave's own row
-    int wave_lds;                 // LDS entries per wave (own row + FP32 edge weights)
+    int own_stride;               // LDS entries of the cell's row
+    int col_lds;                  // LDS entries per column (row twice + FP32 edge weights)
+    int split;                    // waves per column (1, or 2: FP32 with six chunks)
     size_t tab_bytes;             // LDS bytes of the direction tables (before the waves' parts)
 };
 
