@@ -573,16 +573,15 @@ int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
     const DevGrid &G = g->dg;
     const size_t lds = CI.tab_bytes + (size_t)(kColWaves / CI.split) * CI.col_lds * sizeof(Real);
     const int nch = (G.nang + kWave - 1) / kWave;
-    // FP32: edge weights in LDS; six chunks split over two waves
-    if constexpr (sizeof(Real) == 4) {
-        if (CI.split == 2) {
-            if (nch != 6) return RT_EINVAL;
-            hipLaunchKernelGGL((k_column<Real, 3, true, 2>), dim3(CI.grid), dim3(kColBlock), lds, s,
-                               G, CI, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T,
-                               rho, u, ka, ks, dt, dT0, P.sums, P.noroot,
-                               static_cast<Real *>(Istar));
-            return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
-        }
+    // FP32: edge weights in LDS; six chunks split over two waves (the only
+    // six-chunk variant)
+    if (CI.split == 2) {
+        if (nch != 6) return RT_EINVAL;
+        hipLaunchKernelGGL((k_column<Real, 3, sizeof(Real) == 4, 2>), dim3(CI.grid), dim3(kColBlock),
+                           lds, s, G, CI, static_cast<const Real *>(Iin), static_cast<Real *>(Iout),
+                           T, rho, u, ka, ks, dt, dT0, P.sums, P.noroot,
+                           static_cast<Real *>(Istar));
+        return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
     }
     if (CI.split != 1) return RT_EINVAL;
 #define RT_COL(NC)                                                                             \
@@ -599,7 +598,6 @@ int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
         RT_COL(3)
         RT_COL(4)
         RT_COL(5)
-        RT_COL(6)
         default:
             return RT_EINVAL;
     }
@@ -627,9 +625,9 @@ bool column_config(rt_grid *g, int seglen_hint) {
     // 162 5.9 against 7.5 ms)
     const int nch = (G.nang + kWave - 1) / kWave;
     if (nch > 6) return false;
-    // FP32 with six chunks: two waves per column (three chunks each, three
-    // resident waves per SIMD instead of two)
-    CI.split = (real == 4 && nch == 6) ? 2 : 1;
+    // six chunks: two waves per column (three chunks each, three resident
+    // waves per SIMD instead of two)
+    CI.split = nch == 6 ? 2 : 1;
     // one workgroup per quad (pair, when split) of columns along axis 0 (the
     // last of a row may be partly idle) per row and segment
     const int cols_wg = kColWaves / CI.split;
