@@ -416,8 +416,10 @@ def main():
         t5["fp32"] = {"value": p5.ncell * p5.nang * n5 / w5, "ms_per_step": 1e3 * w5 / n5,
                       "ms_per_step_median": 1e3 * sorted(per5)[len(per5) // 2],
                       "no_root_events": st5["no_root"],
-                      "roofline": _roofline("k_column<float, 6> (fused column step: transport "
-                                            "+ angular fluxes + coupling + bookkeeping)",
+                      "roofline": _roofline("k_column<float, 3, true, 2> (fused column step, a "
+                                            "column's six direction chunks over two waves: "
+                                            "transport + angular fluxes + coupling + "
+                                            "bookkeeping)",
                                             "k_column", p5.ncell, p5.nang, per5, FLOPS_CURVED,
                                             "traffic_k_column_c5.json")}
         if not args.no_fp64:
