@@ -170,7 +170,8 @@ def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag, integra
     dt = O.max_dt(O.setup(full), full.cfl)
     dev = torch.device("cuda", 0)
     g = rt.Grid(full, precision)
-    print("[parity] %s uses the %s kernel" % (tag, "tiled" if g.fast_path else "general"), flush=True)
+    print("[parity] %s uses the %s kernel" % (tag, {0: "general", 1: "tiled", 2: "column"}[g.path]),
+          flush=True)
     Ia = _upload_initial(full, g.real_dtype(), dev)
     Ib = torch.empty_like(Ia)
     T = torch.as_tensor(full.T).to(dev)
@@ -224,6 +225,34 @@ def test_c5_full_size_fp32_subbox():
     # theta ~ pi/2) where tau_s reaches 100
     _full_vs_subbox("c5", rt.RT_F32, 2, (150, 58, 10), 12, F32_I, F32_T,
                     "c5 full 256x128x256x362 fp32 2 steps, torus block 12^3")
+
+
+def test_c3_full_size_fp64_subbox():
+    # the FP64 column kernel at the 128x64x128 x 162 Kerr-Schild size
+    _full_vs_subbox("c3", rt.RT_F64, 2, (50, 24, -8), 12, F64_I, F64_T,
+                    "c3 full 128x64x128 fp64 2 steps, block 12^3")
+
+
+def test_c5_full_size_fp64_subbox():
+    # the FP64 column kernel, two waves per column, on the full torus grid
+    # (24 GB per state).  Intensities to 1e-11: with per-cell optical depth up
+    # to 100 the coupling's 1 - alpha_s A2 dt/(4 pi) is about 1/(1 + tau), a
+    # difference that amplifies the last bits of the angle sums (the general
+    # kernel differs from the oracle by 1.5e-12 on this block, the column
+    # kernel by 1.8e-12; T by 8e-16)
+    _full_vs_subbox("c5", rt.RT_F64, 2, (150, 58, 10), 12, 1e-11, F64_T,
+                    "c5 full 256x128x256x362 fp64 2 steps, torus block 12^3")
+
+
+@pytest.mark.parametrize("cfg,origin", [("c2", (-4, 56, 56)), ("c3", (50, 24, -8)),
+                                        ("c5", (150, 58, 10))])
+def test_full_size_fp32_ten_steps_subbox(cfg, origin):
+    # ten steps of the full grid against the oracle on a block with a
+    # 20-cell halo (two cells of PLM reach per step): the FP32 errors stay at
+    # the per-step level over many steps (the long-run drift of the full runs
+    # is measured against the FP64 path in the benchmark notes)
+    _full_vs_subbox(cfg, rt.RT_F32, 10, origin, 12, F32_I, F32_T,
+                    "%s full fp32 10 steps, block 12^3 + halo 20" % cfg)
 
 
 # ------------------------------------------------------------ tiled fast path
