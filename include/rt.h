@@ -251,7 +251,10 @@ int rt_step_noalloc(rt_grid *g, void *stream, const void *I_in, void *I_out, dou
 
 /*
  * Adjoint of rt_step for the functional J = sum over steps of
- * w_s * dt * l(I_s), l the luminosity of rt_step.  Given the state at the
+ * w_s * dt * l(I_s), l the luminosity of rt_step: the step of Sec. 2.2-2.5
+ * (transport of Sec. 2.3-2.4, coupling of Sec. 2.5) differentiated in
+ * reverse order, for gradients of the outgoing luminosity with respect to
+ * the opacities, the gas temperature and the intensities.  Given the state at the
  * start of step s (I_n, T_n, the same fluid, opacities and dt) and
  * lamI_np1 = dJ/dI_{s+1}, lamT_np1 = dJ/dT_{s+1}, it writes
  * lamI_n = dJ/dI_s and lamT_n = dJ/dT_s and adds this step's share of
@@ -307,8 +310,9 @@ int rt_gas_update(rt_grid *g, void *stream, const double *dT0, const double *T_p
 
 /*
  * Running totals since rt_init_grid (synchronises the grid's device):
- * number of cells whose quartic had no positive root (T set to 1e-12), and
- * the energy removed by the |n_0| mask.
+ * number of cells whose quartic of Sec. 2.5 had no positive root (T set to
+ * 1e-12), and the energy removed by the |n_0| mask of Sec. 2.4 (directions
+ * too close to the horizon, whose primitive intensity is set to zero).
  */
 int rt_stats(rt_grid *g, int64_t *no_root_events, double *masked_energy);
 
