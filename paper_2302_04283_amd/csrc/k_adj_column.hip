@@ -118,14 +118,12 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int N = G.nang;
     const int nchT = (N + kWave - 1) / kWave;
-    __shared__ int s_adj[kAcMaxAng * kMaxNbr];
     __shared__ Real s_iom[kAcMaxAng];
     extern __shared__ __align__(16) unsigned char s_dyn[];
     // per wave: two psi rows of the column [2][ostride], then (DMA) the next
     // plane's neighbour rows [16][NCW][64] (I rows 0..7, psi rows 8..15)
     Real *s_row = reinterpret_cast<Real *>(s_dyn) + (size_t)wave * wave_lds;
     Real *s_nb = s_row + 2 * ostride;
-    for (int k = threadIdx.x; k < N * kMaxNbr; k += kAcBlock) s_adj[k] = edge_record(G, k);
     for (int k = threadIdx.x; k < N; k += kAcBlock) s_iom[k] = Real(1.0 / G.domega[k]);
 
     // XCD-aware logical block; the direction slices of a column are
@@ -258,25 +256,28 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
         }
         fl[ch] = f;
     }
-    // the column's angular-edge weights of the lane's directions, and which
-    // edges have the direction on their upwind side (kept in registers: the
-    // edge gather then issues no global load behind the neighbour-row DMA)
+    // the lane's directions' angular edges, kept in registers for the whole
+    // march: the edge's other direction and its signed weight (zero for a
+    // slot past the direction's edges or whose upwind side is the other
+    // direction: the slot then adds nothing)
     const Real *vwrow = vw + (size_t)x.gc * E * 2;
-    Real ew[kMaxNbr][NCW];
-    unsigned eu[NCW];
+    int pe[kMaxNbr][NCW];
+    Real sw[kMaxNbr][NCW], iom[NCW];
 #pragma unroll
     for (int ch = 0; ch < NCW; ++ch) {
         const int m = min(lane + kWave * (cb + ch), N - 1);
-        eu[ch] = 0;
+        iom[ch] = Real(1.0 / G.domega[m]);
 #pragma unroll
         for (int s = 0; s < kMaxNbr; ++s) {
-            ew[s][ch] = Real(0);
+            pe[s][ch] = m;
+            sw[s][ch] = Real(0);
             const int e = G.has_edges ? G.adj_e[m * kMaxNbr + s] : -1;
             if (e < 0) continue;
-            const Real vv = vwrow[2 * e];
-            ew[s][ch] = vwrow[2 * e + 1];
-            const bool up = G.adj_s[m * kMaxNbr + s] > 0 ? vv > Real(0) : vv < Real(0);
-            if (up) eu[ch] |= 1u << s;
+            const Real vv = vwrow[2 * e], ww = vwrow[2 * e + 1];
+            const bool is_lo = G.adj_s[m * kMaxNbr + s] > 0;
+            const bool up = is_lo ? vv > Real(0) : vv < Real(0);
+            pe[s][ch] = is_lo ? G.edge_hi[e] : G.edge_lo[e];
+            if (up) sw[s][ch] = edge_weight(dtR, ww, is_lo);
         }
     }
     // luminosity seed of the lane's directions (used on luminosity faces)
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
 #pragma unroll
     for (int ch = 0; ch < NCW; ++ch)
         seed[ch] = lum_seed<Real>(G, lum_weight, dt, min(lane + kWave * (cb + ch), N - 1));
-    __syncthreads();   // s_adj, s_iom
+    __syncthreads();   // s_iom
     if (!active) return;
 
     const bool zper = G.bc[2][0] == RT_BC_PERIODIC;
@@ -292,20 +293,18 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
     // plane pz of the column, I and psi as stored (the wrapped or edge
     // plane), and what the axis-2 boundary condition makes of them: I keeps
     // the edge cell only for directions leaving through that face (`need`
-    // bit; 0: kept), psi is zero outside a non-periodic boundary.  The
-    // condition is applied where a plane enters the queue, so a prefetched
-    // plane is not waited for when it is issued.
-    auto load_raw = [&](int pz, Real (&dI)[NCW], Real (&dP)[NCW], unsigned &need, bool &inside) {
+    // bit; 0: kept); psi keeps the edge plane, whose 1/dV there is zero (as
+    // in the general gather).  The condition is applied where a plane enters
+    // the queue, so a prefetched plane is not waited for when it is issued.
+    auto load_raw = [&](int pz, Real (&dI)[NCW], Real (&dP)[NCW], unsigned &need) {
         long long zz = pz;
         need = 0;
-        inside = true;
         if (pz < 0 || pz >= G.n2) {
             const int side = pz < 0 ? 0 : 1;
             if (zper) {
                 zz = ((pz % G.n2) + G.n2) % G.n2;
             } else {
                 need = side ? kAzP : kAzN;
-                inside = false;
                 zz = side ? G.n2 - 1 : 0;
             }
         }
@@ -318,12 +317,12 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
             dP[ch] = *at_lane(srcP, n);
         }
     };
-    auto enqueue = [&](const Real (&dI)[NCW], const Real (&dP)[NCW], unsigned need, bool inside,
+    auto enqueue = [&](const Real (&dI)[NCW], const Real (&dP)[NCW], unsigned need,
                        Real (&qI)[NCW], Real (&qP)[NCW]) {
 #pragma unroll
         for (int ch = 0; ch < NCW; ++ch) {
             qI[ch] = (need == 0 || (fl[ch] & need)) ? dI[ch] : Real(0);
-            qP[ch] = inside ? dP[ch] : Real(0);
+            qP[ch] = dP[ch];   // outside: the edge plane, times 1/dV = 0
         }
     };
     // DMA: the sixteen neighbour rows of plane pz (this wave's chunks) and
@@ -379,9 +378,8 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
     for (int p = 0; p < 5; ++p) {
         Real dI[NCW], dP[NCW];
         unsigned need;
-        bool inside;
-        load_raw(z0 - 2 + p, dI, dP, need, inside);
-        enqueue(dI, dP, need, inside, qi[p], qp[p]);
+        load_raw(z0 - 2 + p, dI, dP, need);
+        enqueue(dI, dP, need, qi[p], qp[p]);
     }
     if constexpr (DMA) dma_plane(z0, s_row);
 
@@ -405,8 +403,7 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
         // the column's plane z+3 while this one is computed
         Real ni[NCW], np[NCW];
         unsigned nneed = 0;
-        bool nin = true;
-        if (more) load_raw(z + 3, ni, np, nneed, nin);
+        if (more) load_raw(z + 3, ni, np, nneed);
         // axis-2 faces of this plane: which sign may contribute, the
         // luminosity faces, 1/dV at offsets -2 .. +2
         unsigned zv = 0, zfon = 0;
@@ -460,7 +457,7 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
                     const int k = 4 * a + kk;
                     const int o = kk < 2 ? kk : kk + 1;
                     v[o] = (f & (1u << (kAGhostShift + k))) ? Real(0) : nI[kk][ch];
-                    ps[o] = gface[k] >= 0 ? Real(0) : nP[kk][ch];
+                    ps[o] = nP[kk][ch];   // outside: the edge row, times 1/dV = 0
                     iv[o] = ivn[k];
                     C[kk] = cf[a][kk][ch];
                 }
@@ -493,19 +490,11 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
                 adj_axis(acc[ch], v, ps, ivz, C, fb, zfon, seed[ch], plm, dtR);
             }
             if (G.has_edges) {
-                // branch-free over the six slots: a slot past the direction's
-                // edges (record < 0, trailing) or not upwind keeps the sum
+                // branch-free over the six slots (an unused slot adds 0)
+                const Real a_n = own[m] * iom[ch];
 #pragma unroll
-                for (int s = 0; s < kMaxNbr; ++s) {
-                    const int rec = s_adj[m * kMaxNbr + s];
-                    const bool use = rec >= 0 && ((eu[ch] >> s) & 1u);
-                    const int mm = rec >= 0 ? (rec >> 15) & 0x7fff : m;
-                    const bool is_lo = (rec >> 30) & 1;
-                    const int lo = is_lo ? m : mm, hi = is_lo ? mm : m;
-                    Real t = acc[ch];
-                    edge_add(t, dtR, own[lo], s_iom[lo], own[hi], s_iom[hi], ew[s][ch]);
-                    acc[ch] = use ? t : acc[ch];
-                }
+                for (int s = 0; s < kMaxNbr; ++s)
+                    edge_add(acc[ch], a_n, own[pe[s][ch]], s_iom[pe[s][ch]], sw[s][ch]);
             }
             if (n < N) dst[n] = acc[ch];
         }
@@ -518,7 +507,7 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
                 qp[p][ch] = qp[p + 1][ch];
             }
         }
-        if (more) enqueue(ni, np, nneed, nin, qi[4], qp[4]);
+        if (more) enqueue(ni, np, nneed, qi[4], qp[4]);
     }
 }
 

@@ -74,13 +74,30 @@ __device__ __forceinline__ void face_add(Real &lam, Real lF, Real C, Real d) {
 }
 
 // angular edge between directions lo and hi whose upwind side is the
-// direction itself: dJ/dI_n gains -dt (psi_lo/dOmega_lo - psi_hi/dOmega_hi) w
-// with 1/dOmega rounded to the intensity precision
+// direction n itself: dJ/dI_n gains -dt w (psi_lo/dOmega_lo - psi_hi/dOmega_hi).
+// Seen from n, with p the edge's other direction, that is
+// s (psi_n/dOmega_n - psi_p/dOmega_p) with s = -dt w when n is the lower
+// direction and +dt w when it is the upper one; 1/dOmega is rounded to the
+// intensity precision.  edge_weight forms s; edge_add adds the term given
+// a_n = psi_n/dOmega_n (one product for all of n's edges).  Both fused
+// multiply-adds are written out, so every kernel rounds them alike.
 template <typename Real>
-__device__ __forceinline__ void edge_add(Real &lam, Real dtR, Real psi_lo, Real iom_lo, Real psi_hi,
-                                         Real iom_hi, Real ww) {
-    const Real lF = -dtR * (psi_lo * iom_lo - psi_hi * iom_hi);
-    lam += lF * ww;
+__device__ __forceinline__ Real fmar(Real a, Real b, Real c) {
+    if constexpr (sizeof(Real) == 4)
+        return __builtin_fmaf(a, b, c);
+    else
+        return __builtin_fma(a, b, c);
+}
+
+template <typename Real>
+__device__ __forceinline__ Real edge_weight(Real dtR, Real ww, bool n_is_lo) {
+    const Real s = dtR * ww;
+    return n_is_lo ? -s : s;
+}
+
+template <typename Real>
+__device__ __forceinline__ void edge_add(Real &lam, Real a_n, Real psi_p, Real iom_p, Real s) {
+    lam = fmar(fmar(-psi_p, iom_p, a_n), s, lam);
 }
 
 }  // namespace rt

@@ -315,6 +315,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real 
             const Real *C = static_cast<const Real *>(G.C[a]);
             AxisRows<Real> R;
             axis_rows(G, Iin, x, a, R);
+            // psi rows at offsets -2 .. +2 and their cells' 1/dV; outside a
+            // non-periodic boundary the row is the edge cell's and 1/dV is
+            // zero (psi only enters as psi / dV, so the product is zero)
             const Real *prow[5];
             Real iv[5];
 #pragma unroll
@@ -325,7 +328,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real 
                     idx = ((idx % len) + len) % len;
                     inside = true;
                 }
-                prow[o + 2] = inside ? psi + (x.c + (long long)(idx - coord) * stride) * N : nullptr;
+                const int ridx = inside ? idx : (idx < 0 ? 0 : len - 1);
+                prow[o + 2] = psi + (x.c + (long long)(ridx - coord) * stride) * N;
                 iv[o + 2] = inside ? invV[x.gc + (idx - coord) * gstr] : Real(0);
             }
             // faces at offsets fo = -1 .. 2 (face F between cells F-1 and F)
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real 
                     v[k < 2 ? k : k + 1] = val;
                 }
 #pragma unroll
-                for (int o = 0; o < 5; ++o) ps[o] = prow[o] ? prow[o][n] : Real(0);
+                for (int o = 0; o < 5; ++o) ps[o] = prow[o][n];
 #pragma unroll
                 for (int f = 0; f < 4; ++f) {
                     if (!fvalid[f]) continue;
@@ -393,17 +397,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_transport(DevGrid G, const Real 
             const int n = lane + kWave * ch;
             if (n >= N) continue;
             if (G.has_edges) {
+                const Real a_n = psi[x.c * N + n] * Real(1.0 / G.domega[n]);
 #pragma unroll
                 for (int s = 0; s < kMaxNbr; ++s) {
                     const int e = G.adj_e[n * kMaxNbr + s];
                     if (e < 0) break;
                     const size_t vi = ((size_t)x.gc * G.nedge + e) * 2;
                     const Real vv = vw[vi], ww = vw[vi + 1];
-                    const bool up = G.adj_s[n * kMaxNbr + s] > 0 ? vv > Real(0) : vv < Real(0);
+                    const bool is_lo = G.adj_s[n * kMaxNbr + s] > 0;
+                    const bool up = is_lo ? vv > Real(0) : vv < Real(0);
                     if (!up) continue;
-                    const int lo = G.edge_lo[e], hi = G.edge_hi[e];
-                    edge_add(lam[ch], dtR, psi[x.c * N + lo], Real(1.0 / G.domega[lo]),
-                             psi[x.c * N + hi], Real(1.0 / G.domega[hi]), ww);
+                    const int p = is_lo ? G.edge_hi[e] : G.edge_lo[e];
+                    edge_add(lam[ch], a_n, psi[x.c * N + p], Real(1.0 / G.domega[p]),
+                             edge_weight(dtR, ww, is_lo));
                 }
             }
             lamI0[x.c * N + n] = lam[ch];
