@@ -47,6 +47,38 @@ constexpr int col_waves() {
     return sizeof(Real) == 4 ? (NCH <= 1 ? 4 : (NCH <= 3 ? 3 : 2)) : (NCH <= 2 ? 3 : 2);
 }
 constexpr int kColWaves = kColBlock / kWave;
+// most directions of a column kernel (six chunks); the stride of the
+// unit-vector table's components, a constant so one address serves all three
+constexpr int kColMaxAng = 6 * kWave;
+
+// where the plane loop finds the column's angular-edge data: 0 the edge
+// weights in global memory with the shared edge records (FP64); 1 the
+// column's edge weights staged in LDS (FP32, four or five chunks per wave);
+// 2 the column's edge table in LDS (FP32, up to three chunks per wave): for
+// every direction and edge slot the upwind direction and the signed weight
+constexpr int col_ang_mode(int real_bytes, int nch) {
+    return real_bytes == 4 ? (nch <= 3 ? 2 : 1) : 0;
+}
+
+// one entry of the edge table: the edge term of a direction is w I_up (w
+// zero for a slot past the direction's edges or an edge without motion)
+struct alignas(8) AngEntry {
+    int up;
+    float w;
+};
+
+// angular-flux divergence from the edge table, in slot order with one
+// rounding per term (the same value as angular_div_rec from the records)
+__device__ __forceinline__ float ang_div_table(const AngEntry *__restrict__ t, int stride,
+                                               const float *__restrict__ own, int n) {
+    float div = 0.0f;
+#pragma unroll
+    for (int s = 0; s < kMaxNbr; ++s) {
+        const AngEntry e = t[s * stride + n];
+        div = ang_fma(e.w, own[e.up], div);
+    }
+    return div;
+}
 
 __device__ __forceinline__ void col_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -83,7 +115,8 @@ __device__ __forceinline__ void axis_faces(const Real (&v)[5], bool plm, unsigne
     uhi = hi_p ? v[2] + hl0 : (hi_n ? v[3] - hlp : Real(0));
 }
 
-// VWLDS: the column's edge weights staged in LDS (FP32).  SPL: waves per
+// VWLDS: the column's angular-edge data staged in LDS (FP32; col_ang_mode
+// says which form).  SPL: waves per
 // column; with SPL = 2 the column's direction chunks split over two waves
 // (NCH each) of the same workgroup, which share the cell's row through LDS
 // and add their partial FP64 angle sums there (half 0's first); both then
@@ -108,16 +141,21 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     // angular-edge records -- staged once per workgroup, so the plane loop
     // issues no global load behind the neighbour-row prefetch (vector-memory
     // counters retire in order: a later load's wait would also wait for it)
-    double *s_nhat = reinterpret_cast<double *>(s_dyn);     // [N][3]
-    double *s_dom = s_nhat + 3 * N;                          // [N]
-    int *s_adj = reinterpret_cast<int *>(s_dom + N);         // [N][6]
-    // per column: the cell's row, double-buffered [2][own_stride], the
-    // column's edge weights [2E] (VWLDS)
+    constexpr int AM = VWLDS ? col_ang_mode(4, NCH) : 0;
+    double *s_nhat = reinterpret_cast<double *>(s_dyn);     // [3][kColMaxAng]
+    double *s_dom = s_nhat + 3 * kColMaxAng;                 // [N]
+    int *s_adj = reinterpret_cast<int *>(s_dom + N);         // [N][6] (not with AM 2)
+    // per column: the cell's row, double-buffered [2][own_stride], then the
+    // column's edge weights [2E] (AM 1) or edge table [6][own_stride] (AM 2)
     Real *s_row = reinterpret_cast<Real *>(s_dyn + CI.tab_bytes) + (size_t)wc * CI.col_lds;
     Real *s_vw = s_row + 2 * CI.own_stride;
+    AngEntry *s_ang = reinterpret_cast<AngEntry *>(s_vw);
     __shared__ double s_x[kColWaves][8];   // partial angle sums of each wave (SPL = 2)
-    for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
-    for (int k = threadIdx.x; k < 3 * N; k += kColBlock) s_nhat[k] = G.nhat[k];
+    if constexpr (AM != 2)
+        for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
+    // unit vectors by component, so a wave's reads of one component are
+    // consecutive in LDS
+    for (int k = threadIdx.x; k < 3 * N; k += kColBlock) s_nhat[(k % 3) * kColMaxAng + k / 3] = G.nhat[k];
     for (int k = threadIdx.x; k < N; k += kColBlock) s_dom[k] = G.domega[k];
     __shared__ double s_E0[kColWaves][16];   // E0 of each wave's column
 
@@ -229,11 +267,35 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
         }
         fl[ch] = f;
     }
-    if (VWLDS && active && hh == 0) {
+    if (AM == 1 && active && hh == 0) {
         const Real *row = vw + (size_t)x.gc * E * 2;
         for (int k = lane; k < 2 * E; k += kWave) s_vw[k] = row[k];
     }
-    const Real *vwrow = VWLDS ? s_vw : vw + (size_t)x.gc * E * 2;
+    if constexpr (AM == 2) {
+        // each wave the entries of its own directions: the upwind side of an
+        // edge follows the sign of its angular motion v, the weight is +-w
+        // (+ when the direction is the edge's lower one)
+        if (active) {
+            const Real *row = vw + (size_t)x.gc * E * 2;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int n = lbase + kWave * ch;
+                if (n >= N) continue;
+                for (int sl = 0; sl < kMaxNbr; ++sl) {
+                    AngEntry en{n, 0.0f};
+                    const int e = G.has_edges ? G.adj_e[n * kMaxNbr + sl] : -1;
+                    if (e >= 0) {
+                        const float vv = row[2 * e], ww = row[2 * e + 1];
+                        const float sw = G.adj_s[n * kMaxNbr + sl] > 0 ? ww : -ww;
+                        if (vv > 0.0f) en = AngEntry{G.edge_lo[e], sw};
+                        else if (vv < 0.0f) en = AngEntry{G.edge_hi[e], sw};
+                    }
+                    s_ang[sl * CI.own_stride + n] = en;
+                }
+            }
+        }
+    }
+    const Real *vwrow = AM == 1 ? s_vw : vw + (size_t)x.gc * E * 2;
     __syncthreads();   // direction tables, s_vw
 
     double lum_acc = 0.0, me_acc = 0.0;
@@ -415,7 +477,13 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 }
                 Is[ch] = Real(0);
                 if (n >= N) continue;
-                const Real div = G.has_edges ? angular_div_rec(s_adj, s_own, vwrow, n) : Real(0);
+                Real div = Real(0);
+                if (G.has_edges) {
+                    if constexpr (AM == 2)
+                        div = ang_div_table(s_ang, CI.own_stride, s_own, n);
+                    else
+                        div = angular_div_rec(s_adj, s_own, vwrow, n);
+                }
                 const Real qn_ = gq[ch];
                 const Real Qs = qn_ * Ic - dtR * ivol * dq[ch] - quot(dtR * div, Real(s_dom[n]));
                 if (f & kMsk) {
@@ -444,7 +512,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             for (int ch = 0; ch < NCH; ++ch) {
                 const int n = lbase + kWave * ch;
                 const int m = n < N ? n : 0;
-                const double nbr_ = u0 - fma(u1, s_nhat[3 * m], fma(u2, s_nhat[3 * m + 1], u3 * s_nhat[3 * m + 2]));
+                const double nbr_ = u0 - fma(u1, s_nhat[m], fma(u2, s_nhat[kColMaxAng + m], u3 * s_nhat[2 * kColMaxAng + m]));
                 const double nb2 = nbr_ * nbr_;
                 const double rr = rcp64(nb2 * fma(nbr_, tau, n0));
                 nbv[ch] = nbr_;
@@ -492,9 +560,9 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     const double Ip = fma(n0 * nbr_ * nbrr, I, cS * (nbrr * rr * dn));
                     const double dI = (Ip - I) * s_dom[n];
                     sm[0] += dI;
-                    sm[1] = fma(dI, s_nhat[3 * n], sm[1]);
-                    sm[2] = fma(dI, s_nhat[3 * n + 1], sm[2]);
-                    sm[3] = fma(dI, s_nhat[3 * n + 2], sm[3]);
+                    sm[1] = fma(dI, s_nhat[n], sm[1]);
+                    sm[2] = fma(dI, s_nhat[kColMaxAng + n], sm[2]);
+                    sm[3] = fma(dI, s_nhat[2 * kColMaxAng + n], sm[3]);
                     out = Real(Ip);
                 }
                 if (beam_cell && n == G.beam_angle) out = Real(G.beam_I);
@@ -638,11 +706,17 @@ bool column_config(rt_grid *g, int seglen_hint) {
     CI.nwork = nwork;
     CI.grid = (int)((blocks + 7) / 8 * 8);
     CI.own_stride = (G.nang + 3) / 4 * 4;
+    // as the launcher instantiates: direction chunks per wave and where the
+    // plane loop finds the angular-edge data
+    const int am = col_ang_mode(real, CI.split == 2 ? 3 : nch);
     // direction tables: unit vectors and solid angles (FP64), edge records
-    CI.tab_bytes = ((size_t)G.nang * (4 * sizeof(double) + kMaxNbr * sizeof(int)) + 15) / 16 * 16;
-    // per column, as the launcher instantiates: the cell's row twice, FP32
-    // edge weights
-    CI.col_lds = 2 * CI.own_stride + (real == 4 ? 2 * G.nedge : 0);
+    // (not with the per-column edge table)
+    CI.tab_bytes = (3 * kColMaxAng * sizeof(double) +
+                    (size_t)G.nang * (sizeof(double) + (am == 2 ? 0 : kMaxNbr * sizeof(int))) + 15) /
+                   16 * 16;
+    // per column: the cell's row twice, then the FP32 edge weights or the
+    // edge table (two words an entry)
+    CI.col_lds = 2 * CI.own_stride + (am == 1 ? 2 * G.nedge : (am == 2 ? 2 * kMaxNbr * CI.own_stride : 0));
     // within the default dynamic LDS limit (no attribute call needed)
     return CI.tab_bytes + (size_t)cols_wg * CI.col_lds * real <= 64 * 1024;
 }

@@ -64,6 +64,16 @@ __device__ __forceinline__ Real nbr(const DevGrid &G, const Real *__restrict__ I
     return I[(x.c + (long long)(edge - coord) * stride) * G.nang + n];
 }
 
+// div + w I as one rounding (every kernel's angular gather adds its edge
+// terms this way, so they agree bit for bit)
+template <typename Real>
+__device__ __forceinline__ Real ang_fma(Real w, Real I, Real div) {
+    if constexpr (sizeof(Real) == 4)
+        return __builtin_fmaf(w, I, div);
+    else
+        return __builtin_fma(w, I, div);
+}
+
 // I* of direction n in cell x after the flux divergence (Sec. 2.2 gray
 // integral form) and primitive recovery, zero where masked.  Adds the
 // luminosity-face and masked-energy contributions to the accumulators.
@@ -117,8 +127,7 @@ __device__ __forceinline__ Real transport_dir(const DevGrid &G, const Real *__re
             const Real vv = vw[vi], ww = vw[vi + 1];
             const Real up = vv > Real(0) ? Iin[x.c * N + G.edge_lo[e]]
                                          : (vv < Real(0) ? Iin[x.c * N + G.edge_hi[e]] : Real(0));
-            const Real F = ww * up;
-            div += G.adj_s[n * kMaxNbr + s] > 0 ? F : -F;
+            div = ang_fma(G.adj_s[n * kMaxNbr + s] > 0 ? ww : -ww, up, div);
         }
     }
     const Real qn = q[(size_t)x.gc * N + n];
@@ -285,23 +294,6 @@ __device__ __forceinline__ Real axis_div(const DevGrid &G, const AxisRows<Real> 
     return Fhi - Flo;
 }
 
-// Angular-flux divergence of direction n within the cell's own row.
-template <typename Real>
-__device__ __forceinline__ Real angular_div(const DevGrid &G, const Real *__restrict__ own,
-                                            const Real *__restrict__ vwrow, int n) {
-    Real div = Real(0);
-#pragma unroll
-    for (int s = 0; s < kMaxNbr; ++s) {
-        const int e = G.adj_e[n * kMaxNbr + s];
-        if (e < 0) break;
-        const Real vv = vwrow[2 * e], ww = vwrow[2 * e + 1];
-        const Real up = vv > Real(0) ? own[G.edge_lo[e]] : (vv < Real(0) ? own[G.edge_hi[e]] : Real(0));
-        const Real F = ww * up;
-        div += G.adj_s[n * kMaxNbr + s] > 0 ? F : -F;
-    }
-    return div;
-}
-
 // Largest direction count of the general kernels (8 chunks of 64 lanes).
 constexpr int kMaxAngGeneral = 8 * kWave;
 
@@ -316,7 +308,9 @@ __device__ __forceinline__ int edge_record(const DevGrid &G, int i) {
     return e | (m << 15) | ((is_lo ? 1 : 0) << 30);
 }
 
-// angular_div from staged edge records (the same arithmetic and order).
+// Angular-flux divergence of direction n from staged edge records: with
+// the edge's signed weight +-w (+ when n is the edge's lower direction) and
+// the upwind direction's intensity, div = sum over the edges of +-w I_up.
 template <typename Real>
 __device__ __forceinline__ Real angular_div_rec(const int *__restrict__ rec, const Real *__restrict__ own,
                                                 const Real *__restrict__ vwrow, int n) {
@@ -332,8 +326,7 @@ __device__ __forceinline__ Real angular_div_rec(const int *__restrict__ rec, con
         const Real Im = own[m];
         const Real Ilo = is_lo ? In : Im, Ihi = is_lo ? Im : In;
         const Real up = vv > Real(0) ? Ilo : (vv < Real(0) ? Ihi : Real(0));
-        const Real F = ww * up;
-        div += is_lo ? F : -F;
+        div = ang_fma(is_lo ? ww : -ww, up, div);
     }
     return div;
 }
@@ -398,8 +391,7 @@ __device__ __forceinline__ Real angular_div_mapr(const DevGrid &G, const int *__
         const Real Ilo = own[lo] + grad[2 * lo] * D[0] + grad[2 * lo + 1] * D[1];
         const Real Ihi = own[hi] + grad[2 * hi] * D[2] + grad[2 * hi + 1] * D[3];
         const Real up = vv > Real(0) ? Ilo : (vv < Real(0) ? Ihi : Real(0));
-        const Real F = ww * up;
-        div += is_lo ? F : -F;
+        div = ang_fma(is_lo ? ww : -ww, up, div);
     }
     return div;
 }
@@ -426,8 +418,7 @@ __device__ __forceinline__ Real angular_div_plm(const DevGrid &G, const int *__r
         const Real IL = Ilo + half_slope(own[G.edge_ll[e]], Ilo, Ihi);
         const Real IR = Ihi - half_slope(Ilo, Ihi, own[G.edge_rr[e]]);
         const Real up = vv > Real(0) ? IL : (vv < Real(0) ? IR : Real(0));
-        const Real F = ww * up;
-        div += is_lo ? F : -F;
+        div = ang_fma(is_lo ? ww : -ww, up, div);
     }
     return div;
 }
