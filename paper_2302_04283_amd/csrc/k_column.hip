@@ -115,6 +115,23 @@ __device__ __forceinline__ void axis_faces(const Real (&v)[5], bool plm, unsigne
     uhi = hi_p ? v[2] + hl0 : (hi_n ? v[3] - hlp : Real(0));
 }
 
+// the same face values with one select a face: a direction without motion
+// across a face has a zero coefficient there (C = dA n^a n_0 with n^a = 0),
+// so its value, the other upwind choice here, contributes a zero flux all the
+// same (up to the sign of zero)
+template <typename Real>
+__device__ __forceinline__ void axis_faces2(const Real (&v)[5], bool plm, unsigned lo_p,
+                                            unsigned hi_p, Real &ulo, Real &uhi) {
+    Real hlm = Real(0), hl0 = Real(0), hlp = Real(0);
+    if (plm) {
+        hlm = half_slope(v[0], v[1], v[2]);
+        hl0 = half_slope(v[1], v[2], v[3]);
+        hlp = half_slope(v[2], v[3], v[4]);
+    }
+    ulo = lo_p ? v[1] + hlm : v[2] - hl0;
+    uhi = hi_p ? v[2] + hl0 : v[3] - hlp;
+}
+
 // VWLDS: the column's angular-edge data staged in LDS (FP32; col_ang_mode
 // says which form).  SPL: waves per
 // column; with SPL = 2 the column's direction chunks split over two waves
@@ -235,6 +252,10 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
         }
         ncol[k] = a == 0 ? j * G.n0 + idx : idx * G.n0 + i;
     }
+    // whether a vacuum ghost borders the column along axis 0 or 1 (wave-
+    // uniform: most columns have none and skip the per-direction zeroing)
+    const bool ghost_x = gface[0] >= 0 || gface[1] >= 0 || gface[2] >= 0 || gface[3] >= 0;
+    const bool ghost_y = gface[4] >= 0 || gface[5] >= 0 || gface[6] >= 0 || gface[7] >= 0;
     Real gq[NCH], cxl[NCH], cxh[NCH], cyl[NCH], cyh[NCH], czz[NCH];
     unsigned fl[NCH];
 #pragma unroll
@@ -430,24 +451,32 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 Real nb[4][NCH];
                 if constexpr (RPF) {
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const int k = 4 * a + kk;
+                    for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch)
-                            nb[kk][ch] = (fl[ch] & (1u << (kGhostShift + k))) ? Real(0) : pnb[k][ch];
+                        for (int ch = 0; ch < NCH; ++ch) nb[kk][ch] = pnb[4 * a + kk][ch];
+                    if (a == 0 ? ghost_x : ghost_y) {
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch) {
+                            // the flag tests are formed here, not kept as
+                            // lane masks across the march
+                            unsigned f = fl[ch];
+                            asm volatile("" : "+v"(f));
+#pragma unroll
+                            for (int kk = 0; kk < 4; ++kk)
+                                if (f & (1u << (kGhostShift + 4 * a + kk))) nb[kk][ch] = Real(0);
+                        }
                     }
                 } else {
                     load_axis(z, a, nb);
                 }
-                const unsigned lp = a ? kSylP : kSxlP, ln = a ? kSylN : kSxlN;
-                const unsigned hp = a ? kSyhP : kSxhP, hn = a ? kSyhN : kSxhN;
+                const unsigned lp = a ? kSylP : kSxlP, hp = a ? kSyhP : kSxhP;
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
                     const int n = lbase + kWave * ch;
                     const unsigned f = fl[ch];
                     const Real v[5] = {nb[0][ch], nb[1][ch], qz[1][ch], nb[2][ch], nb[3][ch]};
                     Real ulo, uhi;
-                    axis_faces(v, plm, f & lp, f & ln, f & hp, f & hn, ulo, uhi);
+                    axis_faces2(v, plm, f & lp, f & hp, ulo, uhi);
                     const Real Flo = (a ? cyl[ch] : cxl[ch]) * ulo;
                     const Real Fhi = (a ? cyh[ch] : cxh[ch]) * uhi;
                     if (lum_here && G.lum_axis == a && n < N)
@@ -467,7 +496,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 {
                     const Real v[5] = {Real(0), qz[0][ch], Ic, qz[2][ch], qz[3][ch]};
                     Real ulo, uhi;
-                    axis_faces(v, plm, 0u, 0u, f & kSzP, f & kSzN, ulo, uhi);
+                    axis_faces2(v, plm, 0u, f & kSzP, ulo, uhi);
                     (void)ulo;
                     const Real Flo = Fz[ch], Fhi = czz[ch] * uhi;
                     Fz[ch] = Fhi;
