@@ -30,7 +30,8 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kCellsPerBlock = 16;
 
 // SW lanes per cell (16, 32 or 64; several cells per wavefront when SW < 64),
-// lane l of a group handles directions l, l+SW, ... (NCH of them).  RECOMP:
+// lane l of a group handles directions l, l+SW, ... (NCH of them; every
+// chunk but the last lies wholly below N, so only its indices are clamped).  RECOMP:
 // recompute I* from I_n (else it is read from the forward step's output).
 template <typename Real, int SW, int NCH, bool RECOMP>
 __global__ __launch_bounds__(kBlock) void k_adj_couple(
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     auto fetch = [&](long long c, In &v) {
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const int n = min(lane + SW * ch, N - 1);
+            const int n = (ch < NCH - 1 ? lane + SW * ch : min(lane + SW * ch, N - 1));
             v.I[ch] = Istar[c * N + n];
             v.lp[ch] = lamI1[c * N + n];
         }
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         Real qv[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const int m = min(lane + SW * ch, N - 1);
+            const int m = (ch < NCH - 1 ? lane + SW * ch : min(lane + SW * ch, N - 1));
             if constexpr (kMK) mk[ch] = G.mask[(size_t)x.gc * N + m];
             if constexpr (kQ) qv[ch] = q[(size_t)x.gc * N + m];
         }
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         if constexpr (RECOMP) {
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                const int n = min(lane + SW * ch, N - 1);
+                const int n = (ch < NCH - 1 ? lane + SW * ch : min(lane + SW * ch, N - 1));
                 cur.I[ch] = transport_dir(G, Iin, x, n, dtR, invV[x.gc], dummy_l, dummy_m);
                 cur.lp[ch] = lamI1[x.c * N + n];
             }
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         }
         Real Is[NCH];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) Is[ch] = lane + SW * ch < N ? cur.I[ch] : Real(0);
+        for (int ch = 0; ch < NCH; ++ch) Is[ch] = (ch < NCH - 1 || lane + SW * ch < N) ? cur.I[ch] : Real(0);
         // forward coupling, recomputed.  Per direction: nb = n^0bar (fluid
         // frame), dn = n^0 + nb (alpha_a + alpha_s) dt, rr = 1/(nb^2 dn) and
         // from it idn = 1/dn, k = n^0/dn, 1/(nb dn) = nb rr; w = nb^2 dOmega.
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + SW * ch;
-            live[ch] = n < N && !(kMK ? mk[ch] : G.mask[(size_t)x.gc * N + (n < N ? n : 0)]);
+            live[ch] = (ch < NCH - 1 || n < N) && !(kMK ? mk[ch] : G.mask[(size_t)x.gc * N + (n < N ? n : 0)]);
             const int m = live[ch] ? n : 0;
             const double nb = u0 - fma(u1, s_nh[3 * m], fma(u2, s_nh[3 * m + 1], u3 * s_nh[3 * m + 2]));
             const double nb2 = nb * nb;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + SW * ch;
-            if (n >= N) continue;
+            if (ch == NCH - 1 && n >= N) continue;
             Real out = Real(0);
             if (live[ch]) {
                 const double nb = nbv[ch];
