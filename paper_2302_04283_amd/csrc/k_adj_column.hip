@@ -195,6 +195,10 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
         const int gstr = a == 0 ? (G.g0 > 1 ? 1 : 0) : (G.g1 > 1 ? G.g0 : 0);
         ivn[k] = inside ? invV[x.gc + (idx - coord) * gstr] : Real(0);
     }
+    // whether a vacuum ghost borders the column along axis 0 or 1 (wave-
+    // uniform: most columns have none and skip the per-direction zeroing)
+    const bool ghost_x = gface[0] >= 0 || gface[1] >= 0 || gface[2] >= 0 || gface[3] >= 0;
+    const bool ghost_y = gface[4] >= 0 || gface[5] >= 0 || gface[6] >= 0 || gface[7] >= 0;
     // faces of axes 0 and 1: geometry rows, which sign may contribute, the
     // luminosity faces
     int fg[2][4];
@@ -456,10 +460,19 @@ __global__ __launch_bounds__(kAcBlock) __attribute__((amdgpu_waves_per_eu(acol_w
                 for (int kk = 0; kk < 4; ++kk) {
                     const int k = 4 * a + kk;
                     const int o = kk < 2 ? kk : kk + 1;
-                    v[o] = (f & (1u << (kAGhostShift + k))) ? Real(0) : nI[kk][ch];
+                    v[o] = nI[kk][ch];
                     ps[o] = nP[kk][ch];   // outside: the edge row, times 1/dV = 0
                     iv[o] = ivn[k];
                     C[kk] = cf[a][kk][ch];
+                }
+                if (a == 0 ? ghost_x : ghost_y) {
+                    // the flag tests are formed here, not kept as lane masks
+                    // across the march
+                    unsigned fg = f;
+                    asm volatile("" : "+v"(fg));
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+                        if (fg & (1u << (kAGhostShift + 4 * a + kk))) v[kk < 2 ? kk : kk + 1] = Real(0);
                 }
                 v[2] = qi[2][ch];
                 ps[2] = qp[2][ch];
