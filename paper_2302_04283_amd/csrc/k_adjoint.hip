@@ -31,7 +31,7 @@ constexpr int kCellsPerBlock = 16;
 
 // SW lanes per cell (16, 32 or 64; several cells per wavefront when SW < 64),
 // lane l of a group handles directions l, l+SW, ... (NCH of them; every
-// chunk but the last lies wholly below N, so only its indices are clamped).  RECOMP:
+// chunk but the last lies wholly below N, so only its indices need clamping).  RECOMP:
 // recompute I* from I_n (else it is read from the forward step's output).
 template <typename Real, int SW, int NCH, bool RECOMP>
 __global__ __launch_bounds__(kBlock) void k_adj_couple(
@@ -42,6 +42,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     double *__restrict__ lamT0, double *__restrict__ gka, double *__restrict__ gks,
     const Real *__restrict__ Istar) {
     constexpr int kGroups = kBlock / SW;
+    // unclamped chunk indices (constant offsets from the row base), except
+    // in the FP64 16-lane variant, where they would cost its second wave
+    constexpr bool kOpen = sizeof(Real) == 4 || SW == 64;
     const int lane = threadIdx.x % SW;
     const int grp = threadIdx.x / SW;
     const long long ncell = (long long)G.n0 * G.n1 * G.n2;
@@ -60,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
     auto fetch = [&](long long c, In &v) {
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const int n = (ch < NCH - 1 ? lane + SW * ch : min(lane + SW * ch, N - 1));
+            const int n = (kOpen && ch < NCH - 1 ? lane + SW * ch : min(lane + SW * ch, N - 1));
             v.I[ch] = Istar[c * N + n];
             v.lp[ch] = lamI1[c * N + n];
         }
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         Real qv[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const int m = (ch < NCH - 1 ? lane + SW * ch : min(lane + SW * ch, N - 1));
+            const int m = (kOpen && ch < NCH - 1 ? lane + SW * ch : min(lane + SW * ch, N - 1));
             if constexpr (kMK) mk[ch] = G.mask[(size_t)x.gc * N + m];
             if constexpr (kQ) qv[ch] = q[(size_t)x.gc * N + m];
         }
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         if constexpr (RECOMP) {
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                const int n = (ch < NCH - 1 ? lane + SW * ch : min(lane + SW * ch, N - 1));
+                const int n = (kOpen && ch < NCH - 1 ? lane + SW * ch : min(lane + SW * ch, N - 1));
                 cur.I[ch] = transport_dir(G, Iin, x, n, dtR, invV[x.gc], dummy_l, dummy_m);
                 cur.lp[ch] = lamI1[x.c * N + n];
             }
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
         }
         Real Is[NCH];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) Is[ch] = (ch < NCH - 1 || lane + SW * ch < N) ? cur.I[ch] : Real(0);
+        for (int ch = 0; ch < NCH; ++ch) Is[ch] = ((kOpen && ch < NCH - 1) || lane + SW * ch < N) ? cur.I[ch] : Real(0);
         // forward coupling, recomputed.  Per direction: nb = n^0bar (fluid
         // frame), dn = n^0 + nb (alpha_a + alpha_s) dt, rr = 1/(nb^2 dn) and
         // from it idn = 1/dn, k = n^0/dn, 1/(nb dn) = nb rr; w = nb^2 dOmega.
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + SW * ch;
-            live[ch] = (ch < NCH - 1 || n < N) && !(kMK ? mk[ch] : G.mask[(size_t)x.gc * N + (n < N ? n : 0)]);
+            live[ch] = ((kOpen && ch < NCH - 1) || n < N) && !(kMK ? mk[ch] : G.mask[(size_t)x.gc * N + (n < N ? n : 0)]);
             const int m = live[ch] ? n : 0;
             const double nb = u0 - fma(u1, s_nh[3 * m], fma(u2, s_nh[3 * m + 1], u3 * s_nh[3 * m + 2]));
             const double nb2 = nb * nb;
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_couple(
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int n = lane + SW * ch;
-            if (ch == NCH - 1 && n >= N) continue;
+            if ((!kOpen || ch == NCH - 1) && n >= N) continue;
             Real out = Real(0);
             if (live[ch]) {
                 const double nb = nbv[ch];
