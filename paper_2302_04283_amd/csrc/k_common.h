@@ -12,10 +12,12 @@ constexpr double kFourPi = 12.566370614359172953850573533118;
 // Cross-lane moves for the group sums below, on 32-bit halves.  DPP
 // (quad_perm, row_half_mirror, row_mirror) stays inside a 16-lane row;
 // v_permlane16_swap / v_permlane32_swap (gfx950) exchange rows 0<->1, 2<->3
-// and the two wavefront halves.
+// and the two wavefront halves.  Every lane of these row permutations reads
+// a valid source lane and every row and bank is enabled, so no lane keeps
+// the destination's old value and none needs to be set first.
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp_u(unsigned x) {
-    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
