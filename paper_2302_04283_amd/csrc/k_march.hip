@@ -466,7 +466,7 @@ void k_march(
         const double Ep = Em - rh * G.cv * (Tp - Tm);
         const double Tp2 = Tp * Tp;
         const double S = aa * G.a_rad * Tp2 * Tp2 + as * Ep;
-        const Real cS = Real(dt * S / kFourPi);
+        const Real cS = Real(S * (dt / kFourPi));
         const bool beam_cell = s_beam[cl] != 0;
         Real *dst = Iout + cidx * N;
         Real Ipv[NC];
@@ -475,7 +475,8 @@ void k_march(
             const int n = a + SW * k;
             const Real Ip = fma(kk[k], Is[k], cS * gg[k]);
             Ipv[k] = Ip;
-            Real out = fm[k] ? Real(0) : Ip;
+            // (no masked direction anywhere: the select is skipped, wave-uniform)
+            Real out = (M.any_mask && fm[k]) ? Real(0) : Ip;
             out = (beam_cell && n == G.beam_angle) ? Real(G.beam_I) : out;
             if (k < NC - 1 || n < N) dst[n] = out;
         }
