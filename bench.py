@@ -485,8 +485,8 @@ def main():
         p5l.latlong = (8, 16)
         w5l, _, _ = time_path(p5l, rt.RT_F32, 20, 2, dt, dev)
         out["latlong_8x16_fp32"] = {"value": ncell * 128 * 20 / w5l, "ms_per_step": 1e3 * w5l / 20}
-        # Kerr-Schild, 128 x 64 x 128 cells, 162 directions (column kernel),
-        # and with MAPR angular fluxes (general kernel)
+        # Kerr-Schild, 128 x 64 x 128 cells, 162 directions, DC and MAPR
+        # angular fluxes (column kernel)
         p6 = W.make_problem("c3")
         g6 = rt.Grid(p6, rt.RT_F32, dev.index or 0)
         dt6 = g6.max_dt(p6.cfl)

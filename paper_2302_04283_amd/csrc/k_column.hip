@@ -47,9 +47,32 @@ constexpr int col_waves() {
     return sizeof(Real) == 4 ? (NCH <= 1 ? 4 : (NCH <= 3 ? 3 : 2)) : (NCH <= 2 ? 3 : 2);
 }
 constexpr int kColWaves = kColBlock / kWave;
-// most directions of a column kernel (six chunks); the stride of the
-// unit-vector table's components, a constant so one address serves all three
-constexpr int kColMaxAng = 6 * kWave;
+// Direction tables staged once per workgroup (byte offsets into dynamic
+// LDS): unit vectors by component with a compile-time stride nhs (the
+// instantiation's direction slots, so one address serves all three), solid
+// angles, and with MAPR the candidate planes' inverse matrices and the edge
+// midpoint offsets [E][4] (intensity precision); then the edge records
+// [N][6] (not with the per-column edge table), the MAPR neighbour lists and
+// neighbour counts [N].  The matrices and neighbour lists are component-major
+// in FP32, [24][nhs] and [6][nhs], so a wave's reads of one entry are
+// consecutive; FP64 keeps the direction-major [N][24] and [N][6] (the
+// padded copies would not fit beside four columns' rows at 162 directions).
+struct ColTab {
+    size_t nhat, dom, minv, md, adj, mnb, mcnt, bytes;
+};
+__host__ __device__ inline ColTab col_tab(int N, int E, int nhs, int real, bool adj, bool mapr) {
+    ColTab t{};
+    const size_t nm = real == 4 ? nhs : N;   // rows of the MAPR tables
+    t.nhat = 0;
+    t.dom = t.nhat + (size_t)3 * nhs * sizeof(double);
+    t.minv = t.dom + (size_t)N * sizeof(double);
+    t.md = t.minv + (mapr ? nm * kMaxNbr * 4 * real : 0);
+    t.adj = t.md + (mapr ? (size_t)E * 4 * real : 0);
+    t.mnb = t.adj + (adj ? (size_t)N * kMaxNbr * sizeof(int) : 0);
+    t.mcnt = t.mnb + (mapr ? nm * kMaxNbr * sizeof(int) : 0);
+    t.bytes = (t.mcnt + (mapr ? (size_t)N : 0) + 15) / 16 * 16;
+    return t;
+}
 
 // where the plane loop finds the column's angular-edge data: 0 the edge
 // weights in global memory with the shared edge records (FP64); 1 the
@@ -138,7 +161,7 @@ __device__ __forceinline__ void axis_faces2(const Real (&v)[5], bool plm, unsign
 // (NCH each) of the same workgroup, which share the cell's row through LDS
 // and add their partial FP64 angle sums there (half 0's first); both then
 // solve the same quartic
-template <typename Real, int NCH, bool VWLDS, int SPL>
+template <typename Real, int NCH, bool VWLDS, int SPL, int ANG>
 __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_waves<Real, NCH>()))) void k_column(
     DevGrid G, ColumnInfo CI, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
@@ -158,21 +181,42 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     // angular-edge records -- staged once per workgroup, so the plane loop
     // issues no global load behind the neighbour-row prefetch (vector-memory
     // counters retire in order: a later load's wait would also wait for it)
-    constexpr int AM = VWLDS ? col_ang_mode(4, NCH) : 0;
-    double *s_nhat = reinterpret_cast<double *>(s_dyn);     // [3][kColMaxAng]
-    double *s_dom = s_nhat + 3 * kColMaxAng;                 // [N]
-    int *s_adj = reinterpret_cast<int *>(s_dom + N);         // [N][6] (not with AM 2)
+    // ANG: angular face values, 0 donor cell, 2 MAPR (its gather needs the
+    // edge records and weights, not the edge table)
+    constexpr int AM = VWLDS ? (ANG == 2 ? 1 : col_ang_mode(4, NCH)) : 0;
+    constexpr int NHS = NCH * SPL * kWave;   // unit-vector component stride
+    constexpr bool kMCM = sizeof(Real) == 4;  // MAPR tables component-major
+    const ColTab TB = col_tab(N, E, NHS, sizeof(Real), AM != 2, ANG == 2);
+    double *s_nhat = reinterpret_cast<double *>(s_dyn + TB.nhat);   // [3][NHS]
+    double *s_dom = reinterpret_cast<double *>(s_dyn + TB.dom);     // [N]
+    int *s_adj = reinterpret_cast<int *>(s_dyn + TB.adj);           // [N][6] (not with AM 2)
+    Real *s_minv = reinterpret_cast<Real *>(s_dyn + TB.minv);       // MAPR
+    Real *s_md = reinterpret_cast<Real *>(s_dyn + TB.md);
+    int *s_mnb = reinterpret_cast<int *>(s_dyn + TB.mnb);
+    int8_t *s_mcnt = reinterpret_cast<int8_t *>(s_dyn + TB.mcnt);
     // per column: the cell's row, double-buffered [2][own_stride], then the
-    // column's edge weights [2E] (AM 1) or edge table [6][own_stride] (AM 2)
+    // column's edge weights [2E] (AM 1) or edge table [6][own_stride] (AM 2),
+    // then with MAPR the row's gradients [own_stride][2]
     Real *s_row = reinterpret_cast<Real *>(s_dyn + CI.tab_bytes) + (size_t)wc * CI.col_lds;
     Real *s_vw = s_row + 2 * CI.own_stride;
     AngEntry *s_ang = reinterpret_cast<AngEntry *>(s_vw);
+    Real *s_grad = s_vw + (AM == 1 ? 2 * E : (AM == 2 ? 2 * kMaxNbr * CI.own_stride : 0));
     __shared__ double s_x[kColWaves][8];   // partial angle sums of each wave (SPL = 2)
     if constexpr (AM != 2)
         for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
     // unit vectors by component, so a wave's reads of one component are
     // consecutive in LDS
-    for (int k = threadIdx.x; k < 3 * N; k += kColBlock) s_nhat[(k % 3) * kColMaxAng + k / 3] = G.nhat[k];
+    for (int k = threadIdx.x; k < 3 * N; k += kColBlock) s_nhat[(k % 3) * NHS + k / 3] = G.nhat[k];
+    if constexpr (ANG == 2) {
+        const Real *minv = static_cast<const Real *>(G.mapr_inv);
+        const Real *md = static_cast<const Real *>(G.mapr_d);
+        for (int k = threadIdx.x; k < N * kMaxNbr * 4; k += kColBlock)
+            s_minv[kMCM ? (k % (kMaxNbr * 4)) * NHS + k / (kMaxNbr * 4) : k] = minv[k];
+        for (int k = threadIdx.x; k < E * 4; k += kColBlock) s_md[k] = md[k];
+        for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock)
+            s_mnb[kMCM ? (k % kMaxNbr) * NHS + k / kMaxNbr : k] = G.mapr_nb[k];
+        for (int k = threadIdx.x; k < N; k += kColBlock) s_mcnt[k] = G.mapr_cnt[k];
+    }
     for (int k = threadIdx.x; k < N; k += kColBlock) s_dom[k] = G.domega[k];
     __shared__ double s_E0[kColWaves][16];   // E0 of each wave's column
 
@@ -440,6 +484,32 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 col_wave_sync();
             else
                 __syncthreads();
+            if constexpr (ANG == 2) {
+                // MAPR: every direction's gradient from the cell's row, then
+                // shared with the gather through LDS (the previous plane's
+                // readers passed this plane's row barrier, or, one wave per
+                // column, read in program order)
+                if (G.has_edges) {
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch) {
+                        const int n = lbase + kWave * ch;
+                        if (n >= N) continue;
+                        Real gx, gy;
+                        if constexpr (kMCM)
+                            mapr_gradient_t((int)s_mcnt[n], s_mnb + n, NHS, s_minv + n, NHS, s_own,
+                                            n, gx, gy);
+                        else
+                            mapr_gradient_t((int)s_mcnt[n], s_mnb + n * kMaxNbr, 1,
+                                            s_minv + (size_t)n * kMaxNbr * 4, 1, s_own, n, gx, gy);
+                        s_grad[2 * n] = gx;
+                        s_grad[2 * n + 1] = gy;
+                    }
+                    if constexpr (SPL == 1)
+                        col_wave_sync();
+                    else
+                        __syncthreads();
+                }
+            }
             const bool lum_here = lum_col || (G.lum_axis == 2 && z == (G.lum_side ? G.n2 - 1 : 0));
             // ------------------------------------------------------ transport
             // axis by axis (one axis's neighbour rows live at a time)
@@ -508,7 +578,9 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 if (n >= N) continue;
                 Real div = Real(0);
                 if (G.has_edges) {
-                    if constexpr (AM == 2)
+                    if constexpr (ANG == 2)
+                        div = angular_div_mapr_t(s_md, s_adj, s_own, vwrow, s_grad, n);
+                    else if constexpr (AM == 2)
                         div = ang_div_table(s_ang, CI.own_stride, s_own, n);
                     else
                         div = angular_div_rec(s_adj, s_own, vwrow, n);
@@ -541,7 +613,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             for (int ch = 0; ch < NCH; ++ch) {
                 const int n = lbase + kWave * ch;
                 const int m = n < N ? n : 0;
-                const double nbr_ = u0 - fma(u1, s_nhat[m], fma(u2, s_nhat[kColMaxAng + m], u3 * s_nhat[2 * kColMaxAng + m]));
+                const double nbr_ = u0 - fma(u1, s_nhat[m], fma(u2, s_nhat[NHS + m], u3 * s_nhat[2 * NHS + m]));
                 const double nb2 = nbr_ * nbr_;
                 const double rr = rcp64(nb2 * fma(nbr_, tau, n0));
                 nbv[ch] = nbr_;
@@ -590,8 +662,8 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     const double dI = (Ip - I) * s_dom[n];
                     sm[0] += dI;
                     sm[1] = fma(dI, s_nhat[n], sm[1]);
-                    sm[2] = fma(dI, s_nhat[kColMaxAng + n], sm[2]);
-                    sm[3] = fma(dI, s_nhat[2 * kColMaxAng + n], sm[3]);
+                    sm[2] = fma(dI, s_nhat[NHS + n], sm[2]);
+                    sm[3] = fma(dI, s_nhat[2 * NHS + n], sm[3]);
                     out = Real(Ip);
                 }
                 if (beam_cell && n == G.beam_angle) out = Real(G.beam_I);
@@ -662,44 +734,51 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     }
 }
 
-template <typename Real>
-int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+template <typename Real, int NCH, int SPL, int ANG>
+int launch_col(rt_grid *g, hipStream_t s, size_t lds, const void *Iin, void *Iout, double *T,
+               const double *rho, const double *u, const double *ka, const double *ks, double dt,
+               double *dT0, void *Istar, const Partials &P) {
+    const ColumnInfo &CI = g->column;
+    const auto kern = k_column<Real, NCH, sizeof(Real) == 4, SPL, ANG>;
+    if (ensure_dynamic_lds(reinterpret_cast<const void *>(kern), lds) != RT_OK) return RT_EDEVICE;
+    hipLaunchKernelGGL(kern, dim3(CI.grid), dim3(kColBlock), lds, s, g->dg, CI,
+                       static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho, u, ka, ks,
+                       dt, dT0, P.sums, P.noroot, static_cast<Real *>(Istar));
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
+}
+
+template <typename Real, int ANG>
+int launch_column_a(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                     const double *rho, const double *u, const double *ka, const double *ks,
                     double dt, double *dT0, void *Istar, const Partials &P) {
     const ColumnInfo &CI = g->column;
     const DevGrid &G = g->dg;
     const size_t lds = CI.tab_bytes + (size_t)(kColWaves / CI.split) * CI.col_lds * sizeof(Real);
     const int nch = (G.nang + kWave - 1) / kWave;
-    // FP32: edge weights in LDS; six chunks split over two waves (the only
-    // six-chunk variant)
+    // six chunks split over two waves (the only six-chunk variant)
     if (CI.split == 2) {
         if (nch != 6) return RT_EINVAL;
-        hipLaunchKernelGGL((k_column<Real, 3, sizeof(Real) == 4, 2>), dim3(CI.grid), dim3(kColBlock),
-                           lds, s, G, CI, static_cast<const Real *>(Iin), static_cast<Real *>(Iout),
-                           T, rho, u, ka, ks, dt, dT0, P.sums, P.noroot,
-                           static_cast<Real *>(Istar));
-        return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
+        return launch_col<Real, 3, 2, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
     }
     if (CI.split != 1) return RT_EINVAL;
-#define RT_COL(NC)                                                                             \
-    case NC:                                                                                   \
-        hipLaunchKernelGGL((k_column<Real, NC, sizeof(Real) == 4, 1>),                         \
-                           dim3(CI.grid), dim3(kColBlock), lds, s,                             \
-                           G, CI, static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, \
-                           rho, u, ka, ks, dt, dT0, P.sums, P.noroot,                          \
-                           static_cast<Real *>(Istar));                                        \
-        break;
     switch (nch) {
-        RT_COL(1)
-        RT_COL(2)
-        RT_COL(3)
-        RT_COL(4)
-        RT_COL(5)
-        default:
-            return RT_EINVAL;
+        case 1: return launch_col<Real, 1, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 2: return launch_col<Real, 2, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 3: return launch_col<Real, 3, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 4: return launch_col<Real, 4, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 5: return launch_col<Real, 5, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        default: return RT_EINVAL;
     }
-#undef RT_COL
-    return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
+}
+
+template <typename Real>
+int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                    const double *rho, const double *u, const double *ka, const double *ks,
+                    double dt, double *dT0, void *Istar, const Partials &P) {
+    if (g->dg.ang_recon == 2)
+        return launch_column_a<Real, 2>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+    if (g->dg.ang_recon != 0) return RT_EINVAL;
+    return launch_column_a<Real, 0>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
 }
 
 }  // namespace
@@ -735,19 +814,20 @@ bool column_config(rt_grid *g, int seglen_hint) {
     CI.nwork = nwork;
     CI.grid = (int)((blocks + 7) / 8 * 8);
     CI.own_stride = (G.nang + 3) / 4 * 4;
-    // as the launcher instantiates: direction chunks per wave and where the
-    // plane loop finds the angular-edge data
-    const int am = col_ang_mode(real, CI.split == 2 ? 3 : nch);
-    // direction tables: unit vectors and solid angles (FP64), edge records
-    // (not with the per-column edge table)
-    CI.tab_bytes = (3 * kColMaxAng * sizeof(double) +
-                    (size_t)G.nang * (sizeof(double) + (am == 2 ? 0 : kMaxNbr * sizeof(int))) + 15) /
-                   16 * 16;
+    // as the launcher instantiates: direction chunks per wave, where the
+    // plane loop finds the angular-edge data, the MAPR tables
+    const bool mapr = G.ang_recon == 2;
+    const int nchw = CI.split == 2 ? 3 : nch;
+    const int am = real == 4 ? (mapr ? 1 : col_ang_mode(real, nchw)) : 0;
+    CI.tab_bytes = col_tab(G.nang, G.nedge, nchw * CI.split * kWave, real, am != 2, mapr).bytes;
     // per column: the cell's row twice, then the FP32 edge weights or the
-    // edge table (two words an entry)
-    CI.col_lds = 2 * CI.own_stride + (am == 1 ? 2 * G.nedge : (am == 2 ? 2 * kMaxNbr * CI.own_stride : 0));
-    // within the default dynamic LDS limit (no attribute call needed)
-    return CI.tab_bytes + (size_t)cols_wg * CI.col_lds * real <= 64 * 1024;
+    // edge table (two words an entry), then the MAPR gradients
+    CI.col_lds = 2 * CI.own_stride + (am == 1 ? 2 * G.nedge : (am == 2 ? 2 * kMaxNbr * CI.own_stride : 0)) +
+                 (mapr ? 2 * CI.own_stride : 0);
+    // within the default dynamic LDS limit; with MAPR's tables up to half a
+    // CU's LDS (two workgroups per CU), beyond which the general kernel runs
+    const size_t lds = CI.tab_bytes + (size_t)cols_wg * CI.col_lds * real;
+    return lds <= (mapr ? 80 : 64) * 1024;
 }
 
 int launch_column(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,

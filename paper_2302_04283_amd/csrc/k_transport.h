@@ -339,24 +339,28 @@ __device__ __forceinline__ Real angular_div_rec(const int *__restrict__ rec, con
 // of the intensity precision: 1e-10 in FP64, 1e-5 in FP32.
 template <typename Real>
 __device__ __forceinline__ Real mapr_tie() { return sizeof(Real) == 8 ? Real(1e-10) : Real(1e-5); }
+// (Mn: direction n's candidate matrices, entry 4 i + j at Mn[(4 i + j) ms];
+// nbn: its neighbours, slot s at nbn[s ns]; the general kernel reads the
+// direction-major tables, the column kernel component-major copies in LDS)
 template <typename Real>
-__device__ __forceinline__ void mapr_gradient(const DevGrid &G, const Real *__restrict__ own, int n,
-                                              Real &gx, Real &gy) {
-    const int k = G.mapr_cnt[n];
-    const int *nb = G.mapr_nb + n * kMaxNbr;
-    const Real *M = static_cast<const Real *>(G.mapr_inv) + (size_t)n * kMaxNbr * 4;
+__device__ __forceinline__ void mapr_gradient_t(int k, const int *__restrict__ nbn, int ns,
+                                                const Real *__restrict__ Mn, int ms,
+                                                const Real *__restrict__ own, int n, Real &gx,
+                                                Real &gy) {
     const Real Ic = own[n];
     Real d[kMaxNbr];
 #pragma unroll
-    for (int s = 0; s < kMaxNbr; ++s) d[s] = own[nb[s]] - Ic;
+    for (int s = 0; s < kMaxNbr; ++s) d[s] = own[nbn[s * ns]] - Ic;
     Real cx[kMaxNbr], cy[kMaxNbr], cq[kMaxNbr];
     Real qmin = Real(0);
 #pragma unroll
     for (int i = 0; i < kMaxNbr; ++i) {
         const Real a = d[i], b = d[i + 1 < k ? i + 1 : 0];
-        cx[i] = M[4 * i] * a + M[4 * i + 1] * b;
-        cy[i] = M[4 * i + 2] * a + M[4 * i + 3] * b;
-        cq[i] = cx[i] * cx[i] + cy[i] * cy[i];
+        // every product-sum as written out fused multiply-adds, so every
+        // kernel rounds the candidate slopes (and takes the ties) alike
+        cx[i] = ang_fma(Mn[(4 * i + 1) * ms], b, Mn[(4 * i) * ms] * a);
+        cy[i] = ang_fma(Mn[(4 * i + 3) * ms], b, Mn[(4 * i + 2) * ms] * a);
+        cq[i] = ang_fma(cy[i], cy[i], cx[i] * cx[i]);
         if (i < k && (i == 0 || cq[i] < qmin)) qmin = cq[i];
     }
     const Real lim = qmin * (Real(1) + mapr_tie<Real>());
@@ -369,16 +373,24 @@ __device__ __forceinline__ void mapr_gradient(const DevGrid &G, const Real *__re
             gy = cy[i];
         }
 }
+template <typename Real>
+__device__ __forceinline__ void mapr_gradient(const DevGrid &G, const Real *__restrict__ own, int n,
+                                              Real &gx, Real &gy) {
+    mapr_gradient_t(G.mapr_cnt[n], G.mapr_nb + n * kMaxNbr, 1,
+                    static_cast<const Real *>(G.mapr_inv) + (size_t)n * kMaxNbr * 4, 1, own, n, gx,
+                    gy);
+}
 
 // angular_div with MAPR face values: I + g . d at the edge midpoint, g of
-// the cell the value is taken from (grad holds (gx, gy) per direction).
+// the cell the value is taken from (grad holds (gx, gy) per direction; Dm
+// the edge midpoints' offsets, four per edge).
 template <typename Real>
-__device__ __forceinline__ Real angular_div_mapr(const DevGrid &G, const int *__restrict__ rec,
-                                                 const Real *__restrict__ own,
-                                                 const Real *__restrict__ vwrow,
-                                                 const Real *grad, int n) {
+__device__ __forceinline__ Real angular_div_mapr_t(const Real *__restrict__ Dm,
+                                                   const int *__restrict__ rec,
+                                                   const Real *__restrict__ own,
+                                                   const Real *__restrict__ vwrow,
+                                                   const Real *grad, int n) {
     Real div = Real(0);
-    const Real *Dm = static_cast<const Real *>(G.mapr_d);
 #pragma unroll
     for (int s = 0; s < kMaxNbr; ++s) {
         const int r = rec[n * kMaxNbr + s];
@@ -388,12 +400,19 @@ __device__ __forceinline__ Real angular_div_mapr(const DevGrid &G, const int *__
         const int lo = is_lo ? n : m, hi = is_lo ? m : n;
         const Real vv = vwrow[2 * e], ww = vwrow[2 * e + 1];
         const Real *D = Dm + 4 * e;
-        const Real Ilo = own[lo] + grad[2 * lo] * D[0] + grad[2 * lo + 1] * D[1];
-        const Real Ihi = own[hi] + grad[2 * hi] * D[2] + grad[2 * hi + 1] * D[3];
+        const Real Ilo = ang_fma(grad[2 * lo + 1], D[1], ang_fma(grad[2 * lo], D[0], own[lo]));
+        const Real Ihi = ang_fma(grad[2 * hi + 1], D[3], ang_fma(grad[2 * hi], D[2], own[hi]));
         const Real up = vv > Real(0) ? Ilo : (vv < Real(0) ? Ihi : Real(0));
         div = ang_fma(is_lo ? ww : -ww, up, div);
     }
     return div;
+}
+template <typename Real>
+__device__ __forceinline__ Real angular_div_mapr(const DevGrid &G, const int *__restrict__ rec,
+                                                 const Real *__restrict__ own,
+                                                 const Real *__restrict__ vwrow,
+                                                 const Real *grad, int n) {
+    return angular_div_mapr_t(static_cast<const Real *>(G.mapr_d), rec, own, vwrow, grad, n);
 }
 
 // angular_div with PLM face values (latitude-longitude grids, Sec. 2.3):

@@ -71,18 +71,15 @@ def _cases():
             ("mink-beam", mink), ("c5-odd", c5_odd), ("ks6-outflow-z", ks6_out)]
 
 
-@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
-@pytest.mark.parametrize("name,prob", _cases(), ids=[c[0] for c in _cases()])
-def test_column_kernel_equals_general_kernel(name, prob, prec):
-    p = prob
+def _compare(p, prec, name):
     g = rt.Grid(p, prec)
     dt = g.max_dt(p.cfl)
     auto = g.path
     g.close()
     # the automatic choice: the column kernel in both precisions
     assert auto == 2, (name, auto)
-    print("[column] %s %s n=%s nang=%d" % (name, "fp64" if prec == rt.RT_F64 else "fp32",
-                                           p.n, p.nang), flush=True)
+    print("[column] %s %s n=%s nang=%d ang_recon=%d" % (name, "fp64" if prec == rt.RT_F64 else "fp32",
+                                                        p.n, p.nang, p.ang_recon), flush=True)
     a = _run(p, prec, 3, dt, 2)
     b = _run(p, prec, 3, dt, 1)
     assert a[6] == 2 and b[6] == 0
@@ -113,6 +110,37 @@ def test_column_kernel_equals_general_kernel(name, prob, prec):
     assert a[5]["no_root"] == b[5]["no_root"]
     assert abs(a[5]["masked_energy"] - b[5]["masked_energy"]) <= \
         1e-13 * max(abs(b[5]["masked_energy"]), 1e-300)
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("name,prob", _cases(), ids=[c[0] for c in _cases()])
+def test_column_kernel_equals_general_kernel(name, prob, prec):
+    _compare(prob, prec, name)
+
+
+def _mapr_cases():
+    # MAPR angular face values (Sec. 2.6): the gradients of a plane's row are
+    # formed in LDS before the gather, with the general kernel's helpers
+    l2 = W.make_problem("c3", scale=(9, 7, 6), nlev=2)
+    c4 = W.make_problem("c4", scale=(10, 6, 9))
+    ks_out = W.make_custom("ks_sph", (8, 6, 7), [(2.0, 6.0), (1.0, 2.0), (0.0, 0.7)], 3,
+                           [(1, 1), (1, 1), (1, 1)], M=1.0, a=0.9)
+    ks_out.kappa_a[:] = 0.5
+    ks_out.T[:] = 1.0 + 0.2 * np.arange(ks_out.T.size).reshape(ks_out.T.shape) / ks_out.T.size
+    ks_out.lum_axis, ks_out.lum_side = 2, 0
+    # 162 directions: three chunks per wave (in FP64 the tables and four
+    # columns' rows take 81 KB of LDS, two workgroups per CU)
+    c3 = W.make_problem("c3", scale=(12, 8, 6))
+    cases = [("mapr-l2", l2), ("mapr-c4", c4), ("mapr-outflow-z", ks_out), ("mapr-c3", c3)]
+    for _, p in cases:
+        p.ang_recon = 2
+    return cases
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("name,prob", _mapr_cases(), ids=[c[0] for c in _mapr_cases()])
+def test_column_mapr_equals_general_kernel(name, prob, prec):
+    _compare(prob, prec, name)
 
 
 def _forced(p, prec):

@@ -1,6 +1,7 @@
 """Minimum-angle plane reconstruction (MAPR) on the geodesic grid through the
-C ABI against the oracle (general kernel: Kerr-Schild and flat spherical
-coordinates, geodesic levels 2, 3 and 6).
+C ABI against the oracle (Kerr-Schild and flat spherical coordinates,
+geodesic levels 2, 3 and 6: the column kernel at levels 2 and 3, where its
+MAPR tables fit the LDS budget, the general kernel at level 6).
 
 MAPR picks the flattest candidate plane; planes within a relative 1e-10 of
 the flattest count as equally flat and the first in the neighbour order wins
