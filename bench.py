@@ -416,7 +416,7 @@ def main():
         t5["fp32"] = {"value": p5.ncell * p5.nang * n5 / w5, "ms_per_step": 1e3 * w5 / n5,
                       "ms_per_step_median": 1e3 * sorted(per5)[len(per5) // 2],
                       "no_root_events": st5["no_root"],
-                      "roofline": _roofline("k_column<float, 3, true, 2> (fused column step, a "
+                      "roofline": _roofline("k_column<float, 3, true, 2, 0> (fused column step, a "
                                             "column's six direction chunks over two waves: "
                                             "transport + angular fluxes + coupling + "
                                             "bookkeeping)",
@@ -501,6 +501,22 @@ def main():
         w7, _, st7 = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
         out["kerr_schild_mapr_fp32"] = {"value": p6.ncell * p6.nang * 10 / w7,
                                         "ms_per_step": 1e3 * w7 / 10, "kernel": st7["kernel"]}
+        # the differentiation workload: Kerr-Schild 64 x 32 x 64 cells, 92
+        # directions, 50 steps forward + hand-written adjoint with a
+        # checkpoint every 10 steps, FP32 and FP64 (gradient of the outgoing
+        # luminosity with respect to kappa_a and the gas temperature)
+        p8 = W.make_problem("c4")
+        g8 = rt.Grid(p8, rt.RT_F32, dev.index or 0)
+        dt8 = g8.max_dt(p8.cfl)
+        g8.close()
+        c4 = {"workload": "Kerr-Schild a=0.9, 64x32x64, 92 directions, 50 steps, checkpoint every 10",
+              "steps": 50, "checkpoint_every": 10}
+        for prec8, nm8 in ((rt.RT_F32, "fp32"), (rt.RT_F64, "fp64")):
+            w8, fin8 = time_fwd_adjoint(p8, prec8, 50, 10, dt8, dev)
+            c4[nm8] = {"value": p8.ncell * p8.nang * 50 / w8, "ms_per_step": 1e3 * w8 / 50,
+                       "gradients_finite": fin8}
+        c4["speedup_fp32_over_fp64"] = c4["fp32"]["value"] / c4["fp64"]["value"]
+        out["kerr_schild_64x32x64_fwd_adjoint"] = c4
         print("[bench] context done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
