@@ -471,14 +471,14 @@ def main():
         w3, _, _ = time_path(p3, rt.RT_F32, 10, 2, dt, dev)
         out["two_stage_tau_fp32"] = {"value": ncell * nang * 10 / w3, "ms_per_step": 1e3 * w3 / 10,
                                      "integrator": 2, "tau_coeff": 5.0, "kernel": "general"}
-        # radiation-dominated velocity substitute (general kernel) and the
+        # radiation-dominated velocity substitute (column kernel) and the
         # hand-over of dT0 to the gas (one thread per cell)
         p4 = W.make_problem(CONFIG)
         p4.extras["dev_init64"] = prob.extras["dev_init64"]     # the same field
         p4.rad_velocity = 1
-        w4, _, _ = time_path(p4, rt.RT_F32, 10, 2, dt, dev)
+        w4, _, st4 = time_path(p4, rt.RT_F32, 10, 2, dt, dev)
         out["rad_velocity_fp32"] = {"value": ncell * nang * 10 / w4, "ms_per_step": 1e3 * w4 / 10,
-                                    "kernel": "general",
+                                    "kernel": st4["kernel"],
                                     "gas_update_ms": 1e3 * time_gas_update(p4, dev, 20)}
         # the same box on the latitude-longitude grid, 8 x 16 directions (tiled)
         p5l = W.make_problem(CONFIG)

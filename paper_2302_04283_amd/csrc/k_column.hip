@@ -161,7 +161,7 @@ __device__ __forceinline__ void axis_faces2(const Real (&v)[5], bool plm, unsign
 // (NCH each) of the same workgroup, which share the cell's row through LDS
 // and add their partial FP64 angle sums there (half 0's first); both then
 // solve the same quartic
-template <typename Real, int NCH, bool VWLDS, int SPL, int ANG>
+template <typename Real, int NCH, bool VWLDS, int SPL, int ANG, bool SUB>
 __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_waves<Real, NCH>()))) void k_column(
     DevGrid G, ColumnInfo CI, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
@@ -202,6 +202,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     AngEntry *s_ang = reinterpret_cast<AngEntry *>(s_vw);
     Real *s_grad = s_vw + (AM == 1 ? 2 * E : (AM == 2 ? 2 * kMaxNbr * CI.own_stride : 0));
     __shared__ double s_x[kColWaves][8];   // partial angle sums of each wave (SPL = 2)
+    __shared__ double s_v[kColWaves][8];   // the velocity substitute's partial sums (SPL = 2)
     if constexpr (AM != 2)
         for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
     // unit vectors by component, so a wave's reads of one component are
@@ -601,12 +602,46 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 }
             }
             // ------------------------------------------------------ coupling
-            const double u1 = uvec[3 * c], u2 = uvec[3 * c + 1], u3 = uvec[3 * c + 2];
-            const double u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
+            double u1 = uvec[3 * c], u2 = uvec[3 * c + 1], u3 = uvec[3 * c + 2];
+            double u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
             const double rh = rho[c];
             const double aa = kap_a[c] * rh, as = kap_s[c] * rh;
             const double tau = (aa + as) * dt;
             const double Tm = T[c];
+            if constexpr (SUB) {
+                // radiation-dominated velocity substitute (Sec. 2.5): with the
+                // gas velocity, E = sum I n0bar^2 dOm, R^00, R^0a and
+                // sum n^a n0bar I dOm, then the substituted velocity couples
+                double sv[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int n = lbase + kWave * ch;
+                    if (n >= N || (fl[ch] & kMsk)) continue;
+                    const double nx = s_nhat[n], ny = s_nhat[NHS + n], nz = s_nhat[2 * NHS + n];
+                    const double nb = u0 - fma(u1, nx, fma(u2, ny, u3 * nz));
+                    const double Iw = (double)Is[ch] * s_dom[n];
+                    const double Inb = Iw * nb;
+                    sv[0] = fma(Inb, nb, sv[0]);
+                    sv[1] += Iw;
+                    sv[2] = fma(Iw, nx, sv[2]);
+                    sv[3] = fma(Iw, ny, sv[3]);
+                    sv[4] = fma(Iw, nz, sv[4]);
+                    sv[5] = fma(Inb, nx, sv[5]);
+                    sv[6] = fma(Inb, ny, sv[6]);
+                    sv[7] = fma(Inb, nz, sv[7]);
+                }
+                wave_sum_quads(sv);
+                if constexpr (SPL == 2) {
+                    if (lane == 0) {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) s_v[wave][k] = sv[k];
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) sv[k] = s_v[wc * SPL][k] + s_v[wc * SPL + 1][k];
+                }
+                velocity_substitute(sv, rh, Tm, aa, as, n0, dt, G.cv, G.kb, G.a_rad, u0, u1, u2, u3);
+            }
             double nbv[NCH], rrv[NCH];
             double sf[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -734,12 +769,12 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     }
 }
 
-template <typename Real, int NCH, int SPL, int ANG>
+template <typename Real, int NCH, int SPL, int ANG, bool SUB>
 int launch_col(rt_grid *g, hipStream_t s, size_t lds, const void *Iin, void *Iout, double *T,
                const double *rho, const double *u, const double *ka, const double *ks, double dt,
                double *dT0, void *Istar, const Partials &P) {
     const ColumnInfo &CI = g->column;
-    const auto kern = k_column<Real, NCH, sizeof(Real) == 4, SPL, ANG>;
+    const auto kern = k_column<Real, NCH, sizeof(Real) == 4, SPL, ANG, SUB>;
     if (ensure_dynamic_lds(reinterpret_cast<const void *>(kern), lds) != RT_OK) return RT_EDEVICE;
     hipLaunchKernelGGL(kern, dim3(CI.grid), dim3(kColBlock), lds, s, g->dg, CI,
                        static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho, u, ka, ks,
@@ -747,7 +782,7 @@ int launch_col(rt_grid *g, hipStream_t s, size_t lds, const void *Iin, void *Iou
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
 }
 
-template <typename Real, int ANG>
+template <typename Real, int ANG, bool SUB>
 int launch_column_a(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                     const double *rho, const double *u, const double *ka, const double *ks,
                     double dt, double *dT0, void *Istar, const Partials &P) {
@@ -758,15 +793,15 @@ int launch_column_a(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
     // six chunks split over two waves (the only six-chunk variant)
     if (CI.split == 2) {
         if (nch != 6) return RT_EINVAL;
-        return launch_col<Real, 3, 2, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        return launch_col<Real, 3, 2, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
     }
     if (CI.split != 1) return RT_EINVAL;
     switch (nch) {
-        case 1: return launch_col<Real, 1, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
-        case 2: return launch_col<Real, 2, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
-        case 3: return launch_col<Real, 3, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
-        case 4: return launch_col<Real, 4, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
-        case 5: return launch_col<Real, 5, 1, ANG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 1: return launch_col<Real, 1, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 2: return launch_col<Real, 2, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 3: return launch_col<Real, 3, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 4: return launch_col<Real, 4, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 5: return launch_col<Real, 5, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
         default: return RT_EINVAL;
     }
 }
@@ -775,10 +810,15 @@ template <typename Real>
 int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                     const double *rho, const double *u, const double *ka, const double *ks,
                     double dt, double *dT0, void *Istar, const Partials &P) {
+    // MAPR, or the velocity substitute with DC angular fluxes
+    if (g->dg.rad_velocity) {
+        if (g->dg.ang_recon != 0) return RT_EINVAL;
+        return launch_column_a<Real, 0, true>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+    }
     if (g->dg.ang_recon == 2)
-        return launch_column_a<Real, 2>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        return launch_column_a<Real, 2, false>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
     if (g->dg.ang_recon != 0) return RT_EINVAL;
-    return launch_column_a<Real, 0>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+    return launch_column_a<Real, 0, false>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
 }
 
 }  // namespace

@@ -342,4 +342,44 @@ __device__ __forceinline__ double quartic_root_fast(double B4, double B1, double
     return root_or_floor(T, bad);
 }
 
+// Radiation-dominated velocity substitute (Sec. 2.5), per cell, from the
+// transport result's angle sums with the gas velocity u (sv: E = sum I nb^2
+// dOm, R^00 = sum I dOm, R^0a = sum n^a I dOm and sum n^a nb I dOm, with
+// nb = u0 - u.n): where E > rho + u_gas and the radiation velocity
+// v = R^0a/R^00 is subluminal, each component of u moves toward the
+// radiation's four-velocity by the fraction of the gap that one step of the
+// coupling force closes, clamped to [0, 1]; u0 is recomputed.  Shared by the
+// general and column kernels.
+__device__ __forceinline__ void velocity_substitute(const double (&sv)[8], double rh, double Tm,
+                                                    double aa, double as, double n0, double dt,
+                                                    double cv, double kb, double a_rad,
+                                                    double &u0, double &u1, double &u2,
+                                                    double &u3) {
+    const double ug = rh * cv * Tm;
+    if (!(sv[1] > 0.0 && sv[0] > rh + ug)) return;
+    const double iR = 1.0 / sv[1];
+    const double vr[3] = {sv[2] * iR, sv[3] * iR, sv[4] * iR};
+    const double v2 = vr[0] * vr[0] + vr[1] * vr[1] + vr[2] * vr[2];
+    if (!(v2 < 1.0)) return;
+    const double ur0 = 1.0 / sqrt(1.0 - v2);
+    const double wg = rh + ug + rh * kb * Tm;
+    const double Tm2 = Tm * Tm;
+    const double emit = aa * a_rad * Tm2 * Tm2 + as * sv[0];
+    const double uo[3] = {u1, u2, u3};
+    double un[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double ura = ur0 * vr[a];
+        const double Ga = -emit * uo[a] + (aa + as) * sv[5 + a];
+        const double den = n0 * (wg * ur0 * ura - wg * u0 * uo[a]);
+        double f = den != 0.0 ? Ga * dt / den : 0.0;
+        f = fmin(fmax(f, 0.0), 1.0);
+        un[a] = (1.0 - f) * uo[a] + f * ura;
+    }
+    u1 = un[0];
+    u2 = un[1];
+    u3 = un[2];
+    u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
+}
+
 }  // namespace rt

@@ -218,33 +218,7 @@ __device__ __forceinline__ void step_body(DevGrid G, const Real *__restrict__ Ii
                 sv[7] = fma(Inb, nz, sv[7]);
             }
             wave_sum_quads(sv);
-            const double ug = rh * G.cv * Tm;
-            if (sv[1] > 0.0 && sv[0] > rh + ug) {
-                const double iR = 1.0 / sv[1];
-                const double vr[3] = {sv[2] * iR, sv[3] * iR, sv[4] * iR};
-                const double v2 = vr[0] * vr[0] + vr[1] * vr[1] + vr[2] * vr[2];
-                if (v2 < 1.0) {
-                    const double ur0 = 1.0 / sqrt(1.0 - v2);
-                    const double wg = rh + ug + rh * G.kb * Tm;
-                    const double Tm2 = Tm * Tm;
-                    const double emit = aa * G.a_rad * Tm2 * Tm2 + as * sv[0];
-                    const double uo[3] = {u1, u2, u3};
-                    double un[3];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const double ura = ur0 * vr[a];
-                        const double Ga = -emit * uo[a] + (aa + as) * sv[5 + a];
-                        const double den = n0 * (wg * ur0 * ura - wg * u0 * uo[a]);
-                        double f = den != 0.0 ? Ga * dts / den : 0.0;
-                        f = fmin(fmax(f, 0.0), 1.0);
-                        un[a] = (1.0 - f) * uo[a] + f * ura;
-                    }
-                    u1 = un[0];
-                    u2 = un[1];
-                    u3 = un[2];
-                    u0 = sqrt(fma(u1, u1, fma(u2, u2, fma(u3, u3, 1.0))));
-                }
-            }
+            velocity_substitute(sv, rh, Tm, aa, as, n0, dts, G.cv, G.kb, G.a_rad, u0, u1, u2, u3);
         }
         double nbv[NCH], rrv[NCH];
         double sf[3] = {0.0, 0.0, 0.0};   // Em, A1, A2

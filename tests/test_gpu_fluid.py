@@ -1,6 +1,7 @@
-"""The radiation-dominated velocity substitute (general step kernel) and the
-hand-over of dT0 to the gas (rt_gas_update) against the oracle, through the
-C ABI.
+"""The radiation-dominated velocity substitute (here on the column kernel:
+both grids' geometry is independent of axis 2; the general kernel, with the
+same helpers, elsewhere) and the hand-over of dT0 to the gas (rt_gas_update)
+against the oracle, through the C ABI.
 
 Tolerances: FP64 intensities 1e-12, gas temperature 1e-13 (summation order
 only; the substitute's velocity is a function of FP64 sums on both sides);
