@@ -57,10 +57,13 @@ constexpr int kColWaves = kColBlock / kWave;
 // in FP32, [24][nhs] and [6][nhs], so a wave's reads of one entry are
 // consecutive; FP64 keeps the direction-major [N][24] and [N][6] (the
 // padded copies would not fit beside four columns' rows at 162 directions).
+// With angular PLM (latitude-longitude grids) each edge's outer stencil
+// directions [E] and [E] follow.
 struct ColTab {
-    size_t nhat, dom, minv, md, adj, mnb, mcnt, bytes;
+    size_t nhat, dom, minv, md, adj, mnb, mcnt, ell, err, bytes;
 };
-__host__ __device__ inline ColTab col_tab(int N, int E, int nhs, int real, bool adj, bool mapr) {
+__host__ __device__ inline ColTab col_tab(int N, int E, int nhs, int real, bool adj, bool mapr,
+                                          bool aplm) {
     ColTab t{};
     const size_t nm = real == 4 ? nhs : N;   // rows of the MAPR tables
     t.nhat = 0;
@@ -70,7 +73,9 @@ __host__ __device__ inline ColTab col_tab(int N, int E, int nhs, int real, bool 
     t.adj = t.md + (mapr ? (size_t)E * 4 * real : 0);
     t.mnb = t.adj + (adj ? (size_t)N * kMaxNbr * sizeof(int) : 0);
     t.mcnt = t.mnb + (mapr ? nm * kMaxNbr * sizeof(int) : 0);
-    t.bytes = (t.mcnt + (mapr ? (size_t)N : 0) + 15) / 16 * 16;
+    t.ell = (t.mcnt + (mapr ? (size_t)N : 0) + 3) / 4 * 4;
+    t.err = t.ell + (aplm ? (size_t)E * sizeof(int) : 0);
+    t.bytes = (t.err + (aplm ? (size_t)E * sizeof(int) : 0) + 15) / 16 * 16;
     return t;
 }
 
@@ -181,12 +186,13 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     // angular-edge records -- staged once per workgroup, so the plane loop
     // issues no global load behind the neighbour-row prefetch (vector-memory
     // counters retire in order: a later load's wait would also wait for it)
-    // ANG: angular face values, 0 donor cell, 2 MAPR (its gather needs the
-    // edge records and weights, not the edge table)
-    constexpr int AM = VWLDS ? (ANG == 2 ? 1 : col_ang_mode(4, NCH)) : 0;
+    // ANG: angular face values, 0 donor cell, 1 PLM (latitude-longitude
+    // grids), 2 MAPR (geodesic); PLM and MAPR gather with the edge records
+    // and weights, not the edge table
+    constexpr int AM = VWLDS ? (ANG != 0 ? 1 : col_ang_mode(4, NCH)) : 0;
     constexpr int NHS = NCH * SPL * kWave;   // unit-vector component stride
     constexpr bool kMCM = sizeof(Real) == 4;  // MAPR tables component-major
-    const ColTab TB = col_tab(N, E, NHS, sizeof(Real), AM != 2, ANG == 2);
+    const ColTab TB = col_tab(N, E, NHS, sizeof(Real), AM != 2, ANG == 2, ANG == 1);
     double *s_nhat = reinterpret_cast<double *>(s_dyn + TB.nhat);   // [3][NHS]
     double *s_dom = reinterpret_cast<double *>(s_dyn + TB.dom);     // [N]
     int *s_adj = reinterpret_cast<int *>(s_dyn + TB.adj);           // [N][6] (not with AM 2)
@@ -194,6 +200,8 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     Real *s_md = reinterpret_cast<Real *>(s_dyn + TB.md);
     int *s_mnb = reinterpret_cast<int *>(s_dyn + TB.mnb);
     int8_t *s_mcnt = reinterpret_cast<int8_t *>(s_dyn + TB.mcnt);
+    int *s_ell = reinterpret_cast<int *>(s_dyn + TB.ell);           // angular PLM
+    int *s_err = reinterpret_cast<int *>(s_dyn + TB.err);
     // per column: the cell's row, double-buffered [2][own_stride], then the
     // column's edge weights [2E] (AM 1) or edge table [6][own_stride] (AM 2),
     // then with MAPR the row's gradients [own_stride][2]
@@ -208,6 +216,12 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     // unit vectors by component, so a wave's reads of one component are
     // consecutive in LDS
     for (int k = threadIdx.x; k < 3 * N; k += kColBlock) s_nhat[(k % 3) * NHS + k / 3] = G.nhat[k];
+    if constexpr (ANG == 1) {
+        for (int k = threadIdx.x; k < E; k += kColBlock) {
+            s_ell[k] = G.edge_ll[k];
+            s_err[k] = G.edge_rr[k];
+        }
+    }
     if constexpr (ANG == 2) {
         const Real *minv = static_cast<const Real *>(G.mapr_inv);
         const Real *md = static_cast<const Real *>(G.mapr_d);
@@ -581,6 +595,8 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 if (G.has_edges) {
                     if constexpr (ANG == 2)
                         div = angular_div_mapr_t(s_md, s_adj, s_own, vwrow, s_grad, n);
+                    else if constexpr (ANG == 1)
+                        div = angular_div_plm_t(s_ell, s_err, s_adj, s_own, vwrow, n);
                     else if constexpr (AM == 2)
                         div = ang_div_table(s_ang, CI.own_stride, s_own, n);
                     else
@@ -810,13 +826,15 @@ template <typename Real>
 int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                     const double *rho, const double *u, const double *ka, const double *ks,
                     double dt, double *dT0, void *Istar, const Partials &P) {
-    // MAPR, or the velocity substitute with DC angular fluxes
+    // PLM or MAPR, or the velocity substitute with DC angular fluxes
     if (g->dg.rad_velocity) {
         if (g->dg.ang_recon != 0) return RT_EINVAL;
         return launch_column_a<Real, 0, true>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
     }
     if (g->dg.ang_recon == 2)
         return launch_column_a<Real, 2, false>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+    if (g->dg.ang_recon == 1)
+        return launch_column_a<Real, 1, false>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
     if (g->dg.ang_recon != 0) return RT_EINVAL;
     return launch_column_a<Real, 0, false>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
 }
@@ -856,10 +874,11 @@ bool column_config(rt_grid *g, int seglen_hint) {
     CI.own_stride = (G.nang + 3) / 4 * 4;
     // as the launcher instantiates: direction chunks per wave, where the
     // plane loop finds the angular-edge data, the MAPR tables
-    const bool mapr = G.ang_recon == 2;
+    const bool mapr = G.ang_recon == 2, aplm = G.ang_recon == 1;
     const int nchw = CI.split == 2 ? 3 : nch;
-    const int am = real == 4 ? (mapr ? 1 : col_ang_mode(real, nchw)) : 0;
-    CI.tab_bytes = col_tab(G.nang, G.nedge, nchw * CI.split * kWave, real, am != 2, mapr).bytes;
+    const int am = real == 4 ? (G.ang_recon != 0 ? 1 : col_ang_mode(real, nchw)) : 0;
+    CI.tab_bytes =
+        col_tab(G.nang, G.nedge, nchw * CI.split * kWave, real, am != 2, mapr, aplm).bytes;
     // per column: the cell's row twice, then the FP32 edge weights or the
     // edge table (two words an entry), then the MAPR gradients
     CI.col_lds = 2 * CI.own_stride + (am == 1 ? 2 * G.nedge : (am == 2 ? 2 * kMaxNbr * CI.own_stride : 0)) +

@@ -419,10 +419,14 @@ __device__ __forceinline__ Real angular_div_mapr(const DevGrid &G, const int *__
 // the lo side's value I_lo + delta/2 from (I_ll, I_lo, I_hi) and the hi
 // side's I_hi - delta/2 from (I_lo, I_hi, I_rr); both cells of an edge form
 // the same expression, so the fluxes telescope exactly.
+// (ell, err: each edge's outer stencil directions, from the device tables or
+// an LDS copy)
 template <typename Real>
-__device__ __forceinline__ Real angular_div_plm(const DevGrid &G, const int *__restrict__ rec,
-                                                const Real *__restrict__ own,
-                                                const Real *__restrict__ vwrow, int n) {
+__device__ __forceinline__ Real angular_div_plm_t(const int *__restrict__ ell,
+                                                  const int *__restrict__ err,
+                                                  const int *__restrict__ rec,
+                                                  const Real *__restrict__ own,
+                                                  const Real *__restrict__ vwrow, int n) {
     Real div = Real(0);
     const Real In = own[n];
 #pragma unroll
@@ -434,12 +438,18 @@ __device__ __forceinline__ Real angular_div_plm(const DevGrid &G, const int *__r
         const Real vv = vwrow[2 * e], ww = vwrow[2 * e + 1];
         const Real Im = own[m];
         const Real Ilo = is_lo ? In : Im, Ihi = is_lo ? Im : In;
-        const Real IL = Ilo + half_slope(own[G.edge_ll[e]], Ilo, Ihi);
-        const Real IR = Ihi - half_slope(Ilo, Ihi, own[G.edge_rr[e]]);
+        const Real IL = Ilo + half_slope(own[ell[e]], Ilo, Ihi);
+        const Real IR = Ihi - half_slope(Ilo, Ihi, own[err[e]]);
         const Real up = vv > Real(0) ? IL : (vv < Real(0) ? IR : Real(0));
         div = ang_fma(is_lo ? ww : -ww, up, div);
     }
     return div;
+}
+template <typename Real>
+__device__ __forceinline__ Real angular_div_plm(const DevGrid &G, const int *__restrict__ rec,
+                                                const Real *__restrict__ own,
+                                                const Real *__restrict__ vwrow, int n) {
+    return angular_div_plm_t(G.edge_ll, G.edge_rr, rec, own, vwrow, n);
 }
 
 }  // namespace rt

@@ -172,6 +172,32 @@ def test_column_velocity_substitute_equals_general_kernel(name, prob, prec):
     _compare(prob, prec, name)
 
 
+def _plm_cases():
+    # angular PLM on latitude-longitude grids (Sec. 2.3, across the poles in
+    # the same row at psi + pi): the outer stencil directions staged in LDS,
+    # the general kernel's gather
+    ks = W.make_problem("c3", scale=(10, 8, 4))
+    ks.latlong = (6, 12)
+    ks16 = W.make_problem("c3", scale=(9, 6, 5))
+    ks16.latlong = (8, 16)
+    ks_out = W.make_custom("ks_sph", (8, 6, 7), [(2.0, 6.0), (1.0, 2.0), (0.0, 0.7)], 2,
+                           [(1, 1), (1, 1), (1, 1)], M=1.0, a=0.9)
+    ks_out.kappa_a[:] = 0.5
+    ks_out.T[:] = 1.0 + 0.2 * np.arange(ks_out.T.size).reshape(ks_out.T.shape) / ks_out.T.size
+    ks_out.lum_axis, ks_out.lum_side = 2, 0
+    ks_out.latlong = (6, 12)
+    cases = [("plm-6x12", ks), ("plm-8x16", ks16), ("plm-outflow-z", ks_out)]
+    for _, p in cases:
+        p.ang_recon = 1
+    return cases
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("name,prob", _plm_cases(), ids=[c[0] for c in _plm_cases()])
+def test_column_angular_plm_equals_general_kernel(name, prob, prec):
+    _compare(prob, prec, name)
+
+
 def _forced(p, prec):
     p.kernel = 2
     g = rt.Grid(p, prec)

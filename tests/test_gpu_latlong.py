@@ -1,7 +1,8 @@
 """The latitude-longitude angular grid (DC and angular PLM) through the C ABI
 against the oracle: the tiled kernel on the Minkowski box (no angular
-fluxes), the general kernel on Kerr-Schild and on flat spherical coordinates,
-and the adjoint with DC angular fluxes.
+fluxes), the column kernel on Kerr-Schild and on flat spherical coordinates
+(geometry independent of axis 2; the general kernel with the two-stage
+integrator and the tau flux), and the adjoint with DC angular fluxes.
 
 Tolerances as for the geodesic grid: FP64 intensities 1e-12, gas temperature
 1e-13; FP32 intensities 1e-5, gas temperature 2e-7; FP64 gradients 1e-10.
