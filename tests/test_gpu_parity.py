@@ -164,9 +164,11 @@ def _upload_initial(prob, dtype, dev):
     return out
 
 
-def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag, integrator=1):
+def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag, integrator=1,
+                    ang_recon=0, rad_velocity=0, cond_T=False):
     full = W.make_problem(cfg)
     full.integrator = integrator
+    full.ang_recon, full.rad_velocity = ang_recon, rad_velocity
     dt = O.max_dt(O.setup(full), full.cfl)
     dev = torch.device("cuda", 0)
     g = rt.Grid(full, precision)
@@ -183,6 +185,7 @@ def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag, integra
     halo = 2 * steps * integrator          # PLM reach: two cells per stage
     sub = W.make_problem(cfg, sub=(tuple(o - halo for o in origin), tuple(m + 2 * halo for _ in range(3))))
     sub.integrator = integrator
+    sub.ang_recon, sub.rad_velocity = ang_recon, rad_velocity
     Io, To, _, _, _ = oracle_run(sub, steps, dt)
     N = full.n
     ii = [(origin[a] + np.arange(m)) % N[a] for a in range(3)]
@@ -192,6 +195,13 @@ def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag, integra
     eI = rel_err(Ig, Io[sl, sl, sl])
     eT = float(np.max(np.abs(Tg - To[sl, sl, sl]) / To[sl, sl, sl]))
     _report(tag, e_I=eI, e_T=eT)
+    if cond_T:
+        # T solves the cell's energy balance: relative errors of the
+        # radiation energy reach T amplified by E_rad / (rho c_v T)
+        S = O.setup(sub)
+        cv = sub.kb_mu_mp / (sub.gamma_gas - 1.0)
+        Erad = (np.asarray(sub.initial_intensity()) * S.domega.numpy()).sum(-1)
+        tol_T = tol_T * max(1.0, float(np.max(Erad / (sub.rho * cv * sub.T))))
     assert eI <= tol_I and eT <= tol_T
     g.close()
 
@@ -242,6 +252,23 @@ def test_c5_full_size_fp64_subbox():
     # kernel by 1.8e-12; T by 8e-16)
     _full_vs_subbox("c5", rt.RT_F64, 2, (150, 58, 10), 12, 1e-11, F64_T,
                     "c5 full 256x128x256x362 fp64 2 steps, torus block 12^3")
+
+
+def test_c3_full_size_mapr_subbox_fp64():
+    # MAPR angular fluxes (Sec. 2.6) on the column kernel at the 128x64x128 x
+    # 162 Kerr-Schild size the benchmark times (FP64: the oracle's tie rule)
+    _full_vs_subbox("c3", rt.RT_F64, 2, (50, 24, -8), 12, F64_I, F64_T,
+                    "c3 full 128x64x128 mapr fp64 2 steps, block 12^3", ang_recon=2)
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+def test_c2_full_size_velocity_substitute_subbox(prec):
+    # the radiation-dominated velocity substitute (Sec. 2.5) on the column
+    # kernel at the benchmark's 128^3 x 162 size
+    tol = (F64_I, F64_T) if prec == rt.RT_F64 else (F32_I, F32_T)
+    _full_vs_subbox("c2", prec, 2, (-4, 56, 56), 12, *tol,
+                    "c2 full 128^3 substitute %s 2 steps, block 12^3"
+                    % ("fp64" if prec == rt.RT_F64 else "fp32"), rad_velocity=1, cond_T=True)
 
 
 @pytest.mark.parametrize("cfg,origin", [("c2", (-4, 56, 56)), ("c3", (50, 24, -8)),
