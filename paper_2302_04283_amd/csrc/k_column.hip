@@ -166,13 +166,25 @@ __device__ __forceinline__ void axis_faces2(const Real (&v)[5], bool plm, unsign
 // (NCH each) of the same workgroup, which share the cell's row through LDS
 // and add their partial FP64 angle sums there (half 0's first); both then
 // solve the same quartic
-template <typename Real, int NCH, bool VWLDS, int SPL, int ANG, bool SUB>
+// One stage of the two-stage integrator (STG): Q* = gI q I + gB q Ib - beta
+// dt (flux terms), the coupling starts from gT T + gTb Tb and runs over
+// beta dt, and the bookkeeping and the masked-energy ledger carry the weight
+// wS (the general kernel's stage, term for term).
+template <typename Real>
+struct ColStage {
+    const Real *Ib;
+    const double *Tb;
+    double gI, gB, beta, gT, gTb, wS;
+};
+
+template <typename Real, int NCH, bool VWLDS, int SPL, int ANG, bool SUB, bool STG>
 __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_waves<Real, NCH>()))) void k_column(
     DevGrid G, ColumnInfo CI, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
-    const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt,
+    const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt_step,
     double *__restrict__ dT0, double *__restrict__ partials, int *__restrict__ nr_partial,
-    Real *__restrict__ Istar) {
+    Real *__restrict__ Istar, ColStage<Real> st) {
+    const double dt = STG ? st.beta * dt_step : dt_step;   // this stage's time step
     const int lane = threadIdx.x % kWave;
     // wave-uniform (scalar registers): the column and every row address
     // derived from it
@@ -603,9 +615,13 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                         div = angular_div_rec(s_adj, s_own, vwrow, n);
                 }
                 const Real qn_ = gq[ch];
-                const Real Qs = qn_ * Ic - dtR * ivol * dq[ch] - quot(dtR * div, Real(s_dom[n]));
+                Real Qs = qn_ * Ic;
+                if constexpr (STG) {
+                    if (st.Ib) Qs = Real(st.gI) * Qs + Real(st.gB) * (qn_ * st.Ib[c * N + n]);
+                }
+                Qs = Qs - dtR * ivol * dq[ch] - quot(dtR * div, Real(s_dom[n]));
                 if (f & kMsk) {
-                    me_acc -= volD * s_dom[n] * (double)Qs;
+                    me_acc -= (STG ? st.wS : 1.0) * volD * s_dom[n] * (double)Qs;
                     continue;
                 }
                 Is[ch] = quot(Qs, qn_);
@@ -623,7 +639,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             const double rh = rho[c];
             const double aa = kap_a[c] * rh, as = kap_s[c] * rh;
             const double tau = (aa + as) * dt;
-            const double Tm = T[c];
+            const double Tm = (STG && st.Tb) ? st.gT * T[c] + st.gTb * st.Tb[c] : T[c];
             if constexpr (SUB) {
                 // radiation-dominated velocity substitute (Sec. 2.5): with the
                 // gas velocity, E = sum I n0bar^2 dOm, R^00, R^0a and
@@ -738,7 +754,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 if (lane < 4 && hh == 0 && writes) {
                     const double *E0 = s_E0[wave];
                     const int al = lane;
-                    dT0[4 * c + al] = dpre - n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
+                    dT0[4 * c + al] = dpre - (STG ? st.wS : 1.0) * n0 * (E0[4 * al] * sm[0] + E0[4 * al + 1] * sm[1] +
                                                    E0[4 * al + 2] * sm[2] + E0[4 * al + 3] * sm[3]);
                 }
             }
@@ -785,23 +801,24 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     }
 }
 
-template <typename Real, int NCH, int SPL, int ANG, bool SUB>
+template <typename Real, int NCH, int SPL, int ANG, bool SUB, bool STG>
 int launch_col(rt_grid *g, hipStream_t s, size_t lds, const void *Iin, void *Iout, double *T,
                const double *rho, const double *u, const double *ka, const double *ks, double dt,
-               double *dT0, void *Istar, const Partials &P) {
+               double *dT0, void *Istar, const Partials &P, const ColStage<Real> &st) {
     const ColumnInfo &CI = g->column;
-    const auto kern = k_column<Real, NCH, sizeof(Real) == 4, SPL, ANG, SUB>;
+    const auto kern = k_column<Real, NCH, sizeof(Real) == 4, SPL, ANG, SUB, STG>;
     if (ensure_dynamic_lds(reinterpret_cast<const void *>(kern), lds) != RT_OK) return RT_EDEVICE;
     hipLaunchKernelGGL(kern, dim3(CI.grid), dim3(kColBlock), lds, s, g->dg, CI,
                        static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho, u, ka, ks,
-                       dt, dT0, P.sums, P.noroot, static_cast<Real *>(Istar));
+                       dt, dT0, P.sums, P.noroot, static_cast<Real *>(Istar), st);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
 }
 
-template <typename Real, int ANG, bool SUB>
+template <typename Real, int ANG, bool SUB, bool STG = false>
 int launch_column_a(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                     const double *rho, const double *u, const double *ka, const double *ks,
-                    double dt, double *dT0, void *Istar, const Partials &P) {
+                    double dt, double *dT0, void *Istar, const Partials &P,
+                    const ColStage<Real> &st = ColStage<Real>{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 1.0}) {
     const ColumnInfo &CI = g->column;
     const DevGrid &G = g->dg;
     const size_t lds = CI.tab_bytes + (size_t)(kColWaves / CI.split) * CI.col_lds * sizeof(Real);
@@ -809,15 +826,15 @@ int launch_column_a(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
     // six chunks split over two waves (the only six-chunk variant)
     if (CI.split == 2) {
         if (nch != 6) return RT_EINVAL;
-        return launch_col<Real, 3, 2, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        return launch_col<Real, 3, 2, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
     }
     if (CI.split != 1) return RT_EINVAL;
     switch (nch) {
-        case 1: return launch_col<Real, 1, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
-        case 2: return launch_col<Real, 2, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
-        case 3: return launch_col<Real, 3, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
-        case 4: return launch_col<Real, 4, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
-        case 5: return launch_col<Real, 5, 1, ANG, SUB>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
+        case 1: return launch_col<Real, 1, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        case 2: return launch_col<Real, 2, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        case 3: return launch_col<Real, 3, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        case 4: return launch_col<Real, 4, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        case 5: return launch_col<Real, 5, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
         default: return RT_EINVAL;
     }
 }
@@ -887,6 +904,38 @@ bool column_config(rt_grid *g, int seglen_hint) {
     // CU's LDS (two workgroups per CU), beyond which the general kernel runs
     const size_t lds = CI.tab_bytes + (size_t)cols_wg * CI.col_lds * real;
     return lds <= (mapr ? 80 : 64) * 1024;
+}
+
+// The two-stage (Heun) step on the column path: stage 1 from (I, T) into
+// the stage buffers, stage 2 from them back into (Iout, T) with the blend of
+// both states; the luminosity takes half of each stage.
+template <typename Real>
+int column_rk2_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                 const double *rho, const double *u, const double *ka, const double *ks,
+                 double dt, double *dT0, double *lum, const Partials &P) {
+    const size_t ncell = (size_t)g->dg.n0 * g->dg.n1 * g->dg.n2;
+    if (hipMemcpyAsync(g->stage_T, T, ncell * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+        return RT_EDEVICE;
+    const ColStage<Real> s1{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 0.5};
+    int rc = launch_column_a<Real, 0, false, true>(g, s, Iin, g->stage_I, g->stage_T, rho, u, ka,
+                                                   ks, dt, dT0, nullptr, P, s1);
+    if (rc == RT_OK) rc = launch_finalize(g, s, g->column.grid, 0.5 * dt, lum, P);
+    if (rc != RT_OK) return rc;
+    const ColStage<Real> s2{static_cast<const Real *>(Iin), g->stage_T, 0.5, 0.5, 0.5, 0.5, 0.5, 1.0};
+    rc = launch_column_a<Real, 0, false, true>(g, s, g->stage_I, Iout, T, rho, u, ka, ks, dt, dT0,
+                                               nullptr, P, s2);
+    if (rc == RT_OK) rc = launch_finalize(g, s, g->column.grid, 0.5 * dt, lum, P);
+    return rc;
+}
+
+int launch_column_rk2(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                      const double *rho, const double *u, const double *ka, const double *ks,
+                      double dt, double *dT0, double *lum, const Partials &P) {
+    if (g->dg.ang_recon != 0 || g->dg.rad_velocity || g->dg.tau_coeff > 0.0) return RT_EINVAL;
+    if (g->precision == RT_F32)
+        return column_rk2_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);
+    return column_rk2_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);
 }
 
 int launch_column(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,

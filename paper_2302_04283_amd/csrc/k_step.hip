@@ -567,6 +567,8 @@ int launch_step(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *
         if (rc != RT_OK) return rc;
         return launch_finalize(g, s, g->march.grid, dt, lum, P);
     }
+    if (g->column.enabled && g->integrator == 2)
+        return launch_column_rk2(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);
     if (g->column.enabled) {
         int rc = launch_column(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
         if (rc != RT_OK) return rc;

@@ -159,6 +159,11 @@ bool column_config(rt_grid *g, int seglen_hint);
 int launch_column(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                   const double *rho, const double *u, const double *ka, const double *ks,
                   double dt, double *dT0, void *Istar, const Partials &P);
+// the two-stage integrator on the column path (DC angular fluxes, no tau
+// flux or velocity substitute), both stages' finalisers included
+int launch_column_rk2(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
+                      const double *rho, const double *u, const double *ka, const double *ks,
+                      double dt, double *dT0, double *lum, const Partials &P);
 // k_gas.hip
 int launch_gas_update(rt_grid *g, hipStream_t s, const double *dT0, const double *Tpre,
                       double *rho, double *u, double *T, int32_t *status);

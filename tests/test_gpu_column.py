@@ -29,7 +29,8 @@ def _run(p, prec, steps, dt, kernel):
     path = g.path
     Ia = torch.as_tensor(p.initial_intensity()).to(dev, g.real_dtype())
     Ib = torch.empty_like(Ia)
-    Is = torch.empty_like(Ia)
+    # I* is an output of the one-stage step only
+    Is = torch.empty_like(Ia) if p.integrator == 1 else None
     T = torch.as_tensor(p.T).to(dev)
     rho, u, ka, ks = (torch.as_tensor(x).to(dev) for x in (p.rho, p.u_tet, p.kappa_a, p.kappa_s))
     dT0 = torch.zeros(T.shape + (4,), dtype=torch.float64, device=dev)
@@ -41,7 +42,8 @@ def _run(p, prec, steps, dt, kernel):
     st = g.stats()
     g.close()
     p.kernel = 0
-    return Ia.cpu(), Is.cpu(), T.cpu(), dT0.cpu(), float(lum[0]), st, path
+    Is = Is.cpu() if Is is not None else Ia.cpu()   # (two stages: I in its place)
+    return Ia.cpu(), Is, T.cpu(), dT0.cpu(), float(lum[0]), st, path
 
 
 def _cases():
@@ -195,6 +197,31 @@ def _plm_cases():
 @pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
 @pytest.mark.parametrize("name,prob", _plm_cases(), ids=[c[0] for c in _plm_cases()])
 def test_column_angular_plm_equals_general_kernel(name, prob, prec):
+    _compare(prob, prec, name)
+
+
+def _stage_cases():
+    # the two-stage integrator (two launches per step with the stage
+    # weights), DC angular fluxes
+    c3 = W.make_problem("c3", scale=(16, 12, 8))
+    c4 = W.make_problem("c4", scale=(10, 6, 9))
+    ks_out = W.make_custom("ks_sph", (8, 6, 7), [(2.0, 6.0), (1.0, 2.0), (0.0, 0.7)], 3,
+                           [(1, 1), (1, 1), (1, 1)], M=1.0, a=0.9)
+    ks_out.kappa_a[:] = 0.5
+    ks_out.T[:] = 1.0 + 0.2 * np.arange(ks_out.T.size).reshape(ks_out.T.shape) / ks_out.T.size
+    ks_out.lum_axis, ks_out.lum_side = 2, 0
+    mink = W.make_problem("c2", scale=(6, 5, 7))
+    c5 = W.make_problem("c5", scale=(5, 3, 7))
+    cases = [("rk2-c3", c3), ("rk2-c4", c4), ("rk2-outflow-z", ks_out), ("rk2-mink-beam", mink),
+             ("rk2-c5", c5)]
+    for _, p in cases:
+        p.integrator = 2
+    return cases
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("name,prob", _stage_cases(), ids=[c[0] for c in _stage_cases()])
+def test_column_two_stage_equals_general_kernel(name, prob, prec):
     _compare(prob, prec, name)
 
 
