@@ -416,7 +416,7 @@ def main():
         t5["fp32"] = {"value": p5.ncell * p5.nang * n5 / w5, "ms_per_step": 1e3 * w5 / n5,
                       "ms_per_step_median": 1e3 * sorted(per5)[len(per5) // 2],
                       "no_root_events": st5["no_root"],
-                      "roofline": _roofline("k_column<float, 3, true, 2, 0, false> (fused column step, a "
+                      "roofline": _roofline("k_column<float, 3, true, 2, 0, false, false> (fused column step, a "
                                             "column's six direction chunks over two waves: "
                                             "transport + angular fluxes + coupling + "
                                             "bookkeeping)",
@@ -497,6 +497,14 @@ def main():
         w6d, _, st6d = time_path(p6, rt.RT_F64, 10, 2, dt6, dev)
         out["kerr_schild_128x64x128_fp64"] = {"value": p6.ncell * p6.nang * 10 / w6d,
                                               "ms_per_step": 1e3 * w6d / 10, "kernel": st6d["kernel"]}
+        # the same grid with the two-stage integrator (column kernel, two
+        # launches per step)
+        p6.integrator = 2
+        w6s, _, st6s = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
+        out["kerr_schild_128x64x128_two_stage_fp32"] = {
+            "value": p6.ncell * p6.nang * 10 / w6s, "ms_per_step": 1e3 * w6s / 10,
+            "integrator": 2, "kernel": st6s["kernel"]}
+        p6.integrator = 1
         p6.ang_recon = 2
         w7, _, st7 = time_path(p6, rt.RT_F32, 10, 2, dt6, dev)
         out["kerr_schild_mapr_fp32"] = {"value": p6.ncell * p6.nang * 10 / w7,
