@@ -312,6 +312,20 @@ void k_march(
         const long long cidx = (long long)z * pcells + row;
         double dpre = 0.0;
         if (dT0 && a < 4) dpre = dT0[4 * cidx + a];
+        // the second stage's base state of this plane, likewise read before
+        // the prefetch is issued (FP32; the FP64 kernel has no registers left
+        // for it and reads it where it is used)
+        constexpr bool IBPRE = STG && sizeof(Real) == 4;
+        Real ibv[IBPRE ? NC : 1];
+        if constexpr (IBPRE) {
+            if (st.Ib) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    const int n = a + SW * k;
+                    ibv[k] = (k < NC - 1 || n < N) ? st.Ib[cidx * N + n] : Real(0);
+                }
+            }
+        }
         if (more) {
             load_row(z + 3, row, 0u, qn);
 #pragma unroll
@@ -379,9 +393,13 @@ void k_march(
                 const Real dq = fma(cz, Ibz - Iaz, fma(cy, Iby - Iay, cx * (Ibx - Iax)));
                 Real Qb = Ic;
                 if constexpr (STG) {
-                    if (st.Ib)
-                        Qb = Real(st.gI) * Ic +
-                             Real(st.gB) * ((k < NC - 1 || n < N) ? st.Ib[cidx * N + n] : Real(0));
+                    if (st.Ib) {
+                        if constexpr (IBPRE)
+                            Qb = Real(st.gI) * Ic + Real(st.gB) * ibv[k];
+                        else
+                            Qb = Real(st.gI) * Ic +
+                                 Real(st.gB) * ((k < NC - 1 || n < N) ? st.Ib[cidx * N + n] : Real(0));
+                    }
                 }
                 const int kt = REGTAB ? k : 0;
                 const Real Qs = fma(-dtR, dq, (REGTAB ? tq[kt] : s_tab[n]) * Qb);
