@@ -464,13 +464,13 @@ def main():
         out["two_stage_fp32"] = {"value": ncell * nang * 10 / w2s, "ms_per_step": 1e3 * w2s / 10,
                                  "integrator": 2, "kernel": "tiled"}
         # the production scheme's options: two-stage integrator and the
-        # optical-depth-aware flux (general kernel), same 128^3 x 162 grid
+        # optical-depth-aware flux (column kernel), same 128^3 x 162 grid
         p3 = W.make_problem(CONFIG)
         p3.extras["dev_init64"] = prob.extras["dev_init64"]     # the same field
         p3.integrator, p3.tau_coeff = 2, 5.0
-        w3, _, _ = time_path(p3, rt.RT_F32, 10, 2, dt, dev)
+        w3, _, st3 = time_path(p3, rt.RT_F32, 10, 2, dt, dev)
         out["two_stage_tau_fp32"] = {"value": ncell * nang * 10 / w3, "ms_per_step": 1e3 * w3 / 10,
-                                     "integrator": 2, "tau_coeff": 5.0, "kernel": "general"}
+                                     "integrator": 2, "tau_coeff": 5.0, "kernel": st3["kernel"]}
         # radiation-dominated velocity substitute (column kernel) and the
         # hand-over of dT0 to the gas (one thread per cell)
         p4 = W.make_problem(CONFIG)

@@ -42,9 +42,10 @@ constexpr int kColBand = 16;            // rows along axis 1 of a band of workgr
 // resident waves per SIMD the register allocation is held to: the column's
 // geometry and plane queue live in registers, about 25 VGPRs per direction
 // chunk in FP32 and 40 in FP64 on top of the coupling's working set
-template <typename Real, int NCH>
+template <typename Real, int NCH, bool TAU = false>
 constexpr int col_waves() {
-    return sizeof(Real) == 4 ? (NCH <= 1 ? 4 : (NCH <= 3 ? 3 : 2)) : (NCH <= 2 ? 3 : 2);
+    // (the optical-depth-aware flux's per-direction terms take two waves' worth)
+    return TAU ? 2 : (sizeof(Real) == 4 ? (NCH <= 1 ? 4 : (NCH <= 3 ? 3 : 2)) : (NCH <= 2 ? 3 : 2));
 }
 constexpr int kColWaves = kColBlock / kWave;
 // Direction tables staged once per workgroup (byte offsets into dynamic
@@ -177,8 +178,8 @@ struct ColStage {
     double gI, gB, beta, gT, gTb, wS;
 };
 
-template <typename Real, int NCH, bool VWLDS, int SPL, int ANG, bool SUB, bool STG>
-__global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_waves<Real, NCH>()))) void k_column(
+template <typename Real, int NCH, bool VWLDS, int SPL, int ANG, bool SUB, bool STG, bool TAU>
+__global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_waves<Real, NCH, TAU>()))) void k_column(
     DevGrid G, ColumnInfo CI, const Real *__restrict__ Iin, Real *__restrict__ Iout,
     double *__restrict__ T, const double *__restrict__ rho, const double *__restrict__ uvec,
     const double *__restrict__ kap_a, const double *__restrict__ kap_s, double dt_step,
@@ -223,6 +224,11 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     Real *s_grad = s_vw + (AM == 1 ? 2 * E : (AM == 2 ? 2 * kMaxNbr * CI.own_stride : 0));
     __shared__ double s_x[kColWaves][8];   // partial angle sums of each wave (SPL = 2)
     __shared__ double s_v[kColWaves][8];   // the velocity substitute's partial sums (SPL = 2)
+    // optical-depth-aware flux, per wave and plane: (u^0^, u^a^, alpha_E) of
+    // the cell and its six face neighbours (x-, x+, y-, y+, z-, z+) and the
+    // interpolating factor f of the six faces (x-, x+, y-, y+, z-, z+)
+    __shared__ double s_tau[TAU ? kColWaves : 1][7][5];
+    __shared__ double s_ftau[TAU ? kColWaves : 1][6];
     if constexpr (AM != 2)
         for (int k = threadIdx.x; k < N * kMaxNbr; k += kColBlock) s_adj[k] = edge_record(G, k);
     // unit vectors by component, so a wave's reads of one component are
@@ -471,6 +477,58 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
         Real qz[4][NCH];
 #pragma unroll
         for (int p = 0; p < 4; ++p) load_row(z0 - 1 + p, mycol, qz[p]);
+        // optical-depth-aware flux (Sec. 2): lane k < 7 loads the fluid of the
+        // cell (k = 0) or its face neighbour k at plane pz (a ghost carries the
+        // cell's own fluid, a periodic neighbour wraps); tau_plane forms their
+        // u^0^ and alpha_E and the faces' f = -expm1(-tau^2), tau = tau_coeff
+        // alpha_E dt / u^0^ from the two cells' averages (the full step's dt)
+        const bool zper = G.bc[2][0] == RT_BC_PERIODIC;
+        auto tau_load = [&](int pz, double (&tf)[6]) {
+            long long zz = pz;
+            int col = mycol;
+            if (lane == 1) col = ncol[1];
+            if (lane == 2) col = ncol[2];
+            if (lane == 3) col = ncol[5];
+            if (lane == 4) col = ncol[6];
+            if (lane == 5) zz = pz - 1 < 0 ? (zper ? G.n2 - 1 : pz) : pz - 1;
+            if (lane == 6) zz = pz + 1 >= G.n2 ? (zper ? 0 : pz) : pz + 1;
+            const long long cc = zz * pcells + col;
+            tf[0] = uvec[3 * cc];
+            tf[1] = uvec[3 * cc + 1];
+            tf[2] = uvec[3 * cc + 2];
+            tf[3] = rho[cc];
+            tf[4] = kap_a[cc];
+            tf[5] = kap_s[cc];
+        };
+        auto tau_plane = [&](const double (&tf)[6]) {
+            if (lane < 7) {
+                s_tau[wave][lane][0] = sqrt(1.0 + tf[0] * tf[0] + tf[1] * tf[1] + tf[2] * tf[2]);
+                s_tau[wave][lane][1] = tf[0];
+                s_tau[wave][lane][2] = tf[1];
+                s_tau[wave][lane][3] = tf[2];
+                s_tau[wave][lane][4] = (tf[4] + tf[5]) * tf[3];
+            }
+            col_wave_sync();
+            if (lane < 6) {
+                // face lane: lower faces (even) between neighbour 1 + lane and
+                // the cell, upper faces (odd) between the cell and 1 + lane
+                const int a = (lane & 1) ? 0 : 1 + lane, b = (lane & 1) ? 1 + lane : 0;
+                const double t = G.tau_coeff * (0.5 * (s_tau[wave][a][4] + s_tau[wave][b][4])) *
+                                 dt_step / (0.5 * (s_tau[wave][a][0] + s_tau[wave][b][0]));
+                s_ftau[wave][lane] = -expm1(-t * t);
+            }
+            col_wave_sync();
+        };
+        // fluid-frame n^0bar of direction n in cell k of the block above
+        auto tau_nb = [&](int k, int n) -> double {
+            return s_tau[wave][k][0] - (s_tau[wave][k][1] * s_nhat[n] + s_tau[wave][k][2] * s_nhat[NHS + n] +
+                                        s_tau[wave][k][3] * s_nhat[2 * NHS + n]);
+        };
+        if constexpr (TAU) {
+            double tf[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if (lane < 7) tau_load(z0, tf);
+            tau_plane(tf);
+        }
         Real Fz[NCH];
         {
             Real below[NCH];
@@ -481,6 +539,13 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                 Real ulo, uhi;
                 axis_faces(v, plm, 0u, 0u, fl[ch] & kSzP, fl[ch] & kSzN, ulo, uhi);
                 (void)ulo;
+                if constexpr (TAU) {
+                    // the segment's lower face: between z0-1 (below) and z0
+                    const int m = min(lbase + kWave * ch, N - 1);
+                    double fL, fR;
+                    tau_face(s_ftau[wave][4], tau_nb(5, m), tau_nb(0, m), fL, fR);
+                    uhi *= Real((fl[ch] & kSzP) ? fL : fR);
+                }
                 Fz[ch] = czz[ch] * uhi;
             }
         }
@@ -498,6 +563,12 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             // the column's next plane while this one is computed
             Real qn[NCH];
             unsigned qneed = 0;
+            // the plane's fluid for the optical-depth-aware flux, before the
+            // prefetch as well
+            double tfl[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if constexpr (TAU) {
+                if (lane < 7) tau_load(z, tfl);
+            }
             if (more) qneed = load_raw(z + 3, mycol, qn);
             // the cell's row into LDS for the angular gather (double-buffered:
             // the other buffer's readers finished during the previous plane)
@@ -537,6 +608,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                         __syncthreads();
                 }
             }
+            if constexpr (TAU) tau_plane(tfl);
             const bool lum_here = lum_col || (G.lum_axis == 2 && z == (G.lum_side ? G.n2 - 1 : 0));
             // ------------------------------------------------------ transport
             // axis by axis (one axis's neighbour rows live at a time)
@@ -574,6 +646,16 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     const Real v[5] = {nb[0][ch], nb[1][ch], qz[1][ch], nb[2][ch], nb[3][ch]};
                     Real ulo, uhi;
                     axis_faces2(v, plm, f & lp, f & hp, ulo, uhi);
+                    if constexpr (TAU) {
+                        const int m = min(n, N - 1);
+                        const double nlo = tau_nb(1 + 2 * a, m), nc = tau_nb(0, m);
+                        const double nhi = tau_nb(2 + 2 * a, m);
+                        double fL, fR;
+                        tau_face(s_ftau[wave][2 * a], nlo, nc, fL, fR);
+                        ulo *= Real((f & lp) ? fL : fR);
+                        tau_face(s_ftau[wave][2 * a + 1], nc, nhi, fL, fR);
+                        uhi *= Real((f & hp) ? fL : fR);
+                    }
                     const Real Flo = (a ? cyl[ch] : cxl[ch]) * ulo;
                     const Real Fhi = (a ? cyh[ch] : cxh[ch]) * uhi;
                     if (lum_here && G.lum_axis == a && n < N)
@@ -594,6 +676,12 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     const Real v[5] = {Real(0), qz[0][ch], Ic, qz[2][ch], qz[3][ch]};
                     Real ulo, uhi;
                     axis_faces2(v, plm, 0u, f & kSzP, ulo, uhi);
+                    if constexpr (TAU) {
+                        const int m = min(n, N - 1);
+                        double fL, fR;
+                        tau_face(s_ftau[wave][5], tau_nb(0, m), tau_nb(6, m), fL, fR);
+                        uhi *= Real((f & kSzP) ? fL : fR);
+                    }
                     (void)ulo;
                     const Real Flo = Fz[ch], Fhi = czz[ch] * uhi;
                     Fz[ch] = Fhi;
@@ -801,12 +889,12 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
     }
 }
 
-template <typename Real, int NCH, int SPL, int ANG, bool SUB, bool STG>
+template <typename Real, int NCH, int SPL, int ANG, bool SUB, bool STG, bool TAU>
 int launch_col(rt_grid *g, hipStream_t s, size_t lds, const void *Iin, void *Iout, double *T,
                const double *rho, const double *u, const double *ka, const double *ks, double dt,
                double *dT0, void *Istar, const Partials &P, const ColStage<Real> &st) {
     const ColumnInfo &CI = g->column;
-    const auto kern = k_column<Real, NCH, sizeof(Real) == 4, SPL, ANG, SUB, STG>;
+    const auto kern = k_column<Real, NCH, sizeof(Real) == 4, SPL, ANG, SUB, STG, TAU>;
     if (ensure_dynamic_lds(reinterpret_cast<const void *>(kern), lds) != RT_OK) return RT_EDEVICE;
     hipLaunchKernelGGL(kern, dim3(CI.grid), dim3(kColBlock), lds, s, g->dg, CI,
                        static_cast<const Real *>(Iin), static_cast<Real *>(Iout), T, rho, u, ka, ks,
@@ -814,7 +902,7 @@ int launch_col(rt_grid *g, hipStream_t s, size_t lds, const void *Iin, void *Iou
     return hipGetLastError() == hipSuccess ? RT_OK : RT_EDEVICE;
 }
 
-template <typename Real, int ANG, bool SUB, bool STG = false>
+template <typename Real, int ANG, bool SUB, bool STG = false, bool TAU = false>
 int launch_column_a(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                     const double *rho, const double *u, const double *ka, const double *ks,
                     double dt, double *dT0, void *Istar, const Partials &P,
@@ -826,15 +914,15 @@ int launch_column_a(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, doub
     // six chunks split over two waves (the only six-chunk variant)
     if (CI.split == 2) {
         if (nch != 6) return RT_EINVAL;
-        return launch_col<Real, 3, 2, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        return launch_col<Real, 3, 2, ANG, SUB, STG, TAU>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
     }
     if (CI.split != 1) return RT_EINVAL;
     switch (nch) {
-        case 1: return launch_col<Real, 1, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
-        case 2: return launch_col<Real, 2, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
-        case 3: return launch_col<Real, 3, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
-        case 4: return launch_col<Real, 4, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
-        case 5: return launch_col<Real, 5, 1, ANG, SUB, STG>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        case 1: return launch_col<Real, 1, 1, ANG, SUB, STG, TAU>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        case 2: return launch_col<Real, 2, 1, ANG, SUB, STG, TAU>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        case 3: return launch_col<Real, 3, 1, ANG, SUB, STG, TAU>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        case 4: return launch_col<Real, 4, 1, ANG, SUB, STG, TAU>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
+        case 5: return launch_col<Real, 5, 1, ANG, SUB, STG, TAU>(g, s, lds, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P, st);
         default: return RT_EINVAL;
     }
 }
@@ -843,7 +931,13 @@ template <typename Real>
 int launch_column_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                     const double *rho, const double *u, const double *ka, const double *ks,
                     double dt, double *dT0, void *Istar, const Partials &P) {
-    // PLM or MAPR, or the velocity substitute with DC angular fluxes
+    // PLM or MAPR, or the velocity substitute or the optical-depth-aware
+    // flux with DC angular fluxes
+    if (g->dg.tau_coeff > 0.0) {
+        if (g->dg.ang_recon != 0 || g->dg.rad_velocity) return RT_EINVAL;
+        return launch_column_a<Real, 0, false, false, true>(g, s, Iin, Iout, T, rho, u, ka, ks, dt,
+                                                            dT0, Istar, P);
+    }
     if (g->dg.rad_velocity) {
         if (g->dg.ang_recon != 0) return RT_EINVAL;
         return launch_column_a<Real, 0, true>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, Istar, P);
@@ -918,13 +1012,18 @@ int column_rk2_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double 
         hipSuccess)
         return RT_EDEVICE;
     const ColStage<Real> s1{nullptr, nullptr, 1.0, 0.0, 1.0, 1.0, 0.0, 0.5};
-    int rc = launch_column_a<Real, 0, false, true>(g, s, Iin, g->stage_I, g->stage_T, rho, u, ka,
-                                                   ks, dt, dT0, nullptr, P, s1);
+    const bool tau = g->dg.tau_coeff > 0.0;
+    int rc = tau ? launch_column_a<Real, 0, false, true, true>(g, s, Iin, g->stage_I, g->stage_T, rho,
+                                                              u, ka, ks, dt, dT0, nullptr, P, s1)
+                 : launch_column_a<Real, 0, false, true>(g, s, Iin, g->stage_I, g->stage_T, rho, u,
+                                                         ka, ks, dt, dT0, nullptr, P, s1);
     if (rc == RT_OK) rc = launch_finalize(g, s, g->column.grid, 0.5 * dt, lum, P);
     if (rc != RT_OK) return rc;
     const ColStage<Real> s2{static_cast<const Real *>(Iin), g->stage_T, 0.5, 0.5, 0.5, 0.5, 0.5, 1.0};
-    rc = launch_column_a<Real, 0, false, true>(g, s, g->stage_I, Iout, T, rho, u, ka, ks, dt, dT0,
-                                               nullptr, P, s2);
+    rc = tau ? launch_column_a<Real, 0, false, true, true>(g, s, g->stage_I, Iout, T, rho, u, ka, ks,
+                                                          dt, dT0, nullptr, P, s2)
+             : launch_column_a<Real, 0, false, true>(g, s, g->stage_I, Iout, T, rho, u, ka, ks, dt,
+                                                     dT0, nullptr, P, s2);
     if (rc == RT_OK) rc = launch_finalize(g, s, g->column.grid, 0.5 * dt, lum, P);
     return rc;
 }
@@ -932,7 +1031,7 @@ int column_rk2_t(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double 
 int launch_column_rk2(rt_grid *g, hipStream_t s, const void *Iin, void *Iout, double *T,
                       const double *rho, const double *u, const double *ka, const double *ks,
                       double dt, double *dT0, double *lum, const Partials &P) {
-    if (g->dg.ang_recon != 0 || g->dg.rad_velocity || g->dg.tau_coeff > 0.0) return RT_EINVAL;
+    if (g->dg.ang_recon != 0 || g->dg.rad_velocity) return RT_EINVAL;
     if (g->precision == RT_F32)
         return column_rk2_t<float>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);
     return column_rk2_t<double>(g, s, Iin, Iout, T, rho, u, ka, ks, dt, dT0, lum, P);

@@ -266,11 +266,13 @@ int rt_init_grid(const rt_grid_desc *d, int device, rt_grid **out) {
         }
         // column march for geometry independent of axis 2 (one-stage step
         // with DC, PLM or MAPR angular fluxes, or DC with the velocity
-        // substitute; the two-stage step with DC angular fluxes)
+        // substitute; DC with the two-stage step and/or the optical-depth-
+        // aware flux)
         g->column.enabled = 0;
         if (!g->march.enabled && d->kernel != 1 && d->geo_extent[2] == 1 &&
             (g->integrator == 1 || (d->ang_recon == 0 && !d->rad_velocity)) &&
-            !(d->tau_coeff > 0.0) && (!d->rad_velocity || d->ang_recon == 0) &&
+            (!(d->tau_coeff > 0.0) || (d->ang_recon == 0 && !d->rad_velocity)) &&
+            (!d->rad_velocity || d->ang_recon == 0) &&
             (N + rt::kWave - 1) / rt::kWave <= rt::kMaxChunks)
             g->column.enabled = rt::column_config(g, d->seglen) ? 1 : 0;
         // this device's static scratch for rt_step_noalloc (looked up once per

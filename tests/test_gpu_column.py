@@ -29,8 +29,8 @@ def _run(p, prec, steps, dt, kernel):
     path = g.path
     Ia = torch.as_tensor(p.initial_intensity()).to(dev, g.real_dtype())
     Ib = torch.empty_like(Ia)
-    # I* is an output of the one-stage step only
-    Is = torch.empty_like(Ia) if p.integrator == 1 else None
+    # I* is an output of the one-stage step without the tau flux only
+    Is = torch.empty_like(Ia) if p.integrator == 1 and not p.tau_coeff > 0 else None
     T = torch.as_tensor(p.T).to(dev)
     rho, u, ka, ks = (torch.as_tensor(x).to(dev) for x in (p.rho, p.u_tet, p.kappa_a, p.kappa_s))
     dT0 = torch.zeros(T.shape + (4,), dtype=torch.float64, device=dev)
@@ -42,7 +42,7 @@ def _run(p, prec, steps, dt, kernel):
     st = g.stats()
     g.close()
     p.kernel = 0
-    Is = Is.cpu() if Is is not None else Ia.cpu()   # (two stages: I in its place)
+    Is = Is.cpu() if Is is not None else Ia.cpu()   # (no I* output: I in its place)
     return Ia.cpu(), Is, T.cpu(), dT0.cpu(), float(lum[0]), st, path
 
 
@@ -222,6 +222,32 @@ def _stage_cases():
 @pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
 @pytest.mark.parametrize("name,prob", _stage_cases(), ids=[c[0] for c in _stage_cases()])
 def test_column_two_stage_equals_general_kernel(name, prob, prec):
+    _compare(prob, prec, name)
+
+
+def _tau_cases():
+    # the optical-depth-aware flux (C_tau = 5): the fluid of the cell and its
+    # six face neighbours per plane, the general kernel's face factors; one
+    # stage and two stages, periodic and outflow ends along the march
+    cases = []
+    for integ in (1, 2):
+        c3 = W.make_problem("c3", scale=(16, 12, 8))
+        ks_out = W.make_custom("ks_sph", (8, 6, 7), [(2.0, 6.0), (1.0, 2.0), (0.0, 0.7)], 3,
+                               [(1, 1), (1, 1), (1, 1)], M=1.0, a=0.9)
+        ks_out.kappa_a[:] = 0.5
+        ks_out.T[:] = 1.0 + 0.2 * np.arange(ks_out.T.size).reshape(ks_out.T.shape) / ks_out.T.size
+        ks_out.lum_axis, ks_out.lum_side = 2, 0
+        mink = W.make_problem("c2", scale=(6, 5, 7))
+        c5 = W.make_problem("c5", scale=(5, 3, 7))
+        for name, p in (("c3", c3), ("outflow-z", ks_out), ("mink-beam", mink), ("c5", c5)):
+            p.integrator, p.tau_coeff = integ, 5.0
+            cases.append(("tau%d-%s" % (integ, name), p))
+    return cases
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+@pytest.mark.parametrize("name,prob", _tau_cases(), ids=[c[0] for c in _tau_cases()])
+def test_column_tau_flux_equals_general_kernel(name, prob, prec):
     _compare(prob, prec, name)
 
 
