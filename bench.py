@@ -416,7 +416,7 @@ def main():
         t5["fp32"] = {"value": p5.ncell * p5.nang * n5 / w5, "ms_per_step": 1e3 * w5 / n5,
                       "ms_per_step_median": 1e3 * sorted(per5)[len(per5) // 2],
                       "no_root_events": st5["no_root"],
-                      "roofline": _roofline("k_column<float, 3, true, 2, 0, false, false> (fused column step, a "
+                      "roofline": _roofline("k_column<float, 3, true, 2, 0, false, false, false> (fused column step, a "
                                             "column's six direction chunks over two waves: "
                                             "transport + angular fluxes + coupling + "
                                             "bookkeeping)",
