@@ -608,7 +608,13 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                         __syncthreads();
                 }
             }
-            if constexpr (TAU) tau_plane(tfl);
+            // 1/n^0bar of each direction in the cell (it borders all six faces)
+            double tinc[TAU ? NCH : 1];
+            if constexpr (TAU) {
+                tau_plane(tfl);
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) tinc[ch] = 1.0 / tau_nb(0, min(lbase + kWave * ch, N - 1));
+            }
             const bool lum_here = lum_col || (G.lum_axis == 2 && z == (G.lum_side ? G.n2 - 1 : 0));
             // ------------------------------------------------------ transport
             // axis by axis (one axis's neighbour rows live at a time)
@@ -648,12 +654,12 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     axis_faces2(v, plm, f & lp, f & hp, ulo, uhi);
                     if constexpr (TAU) {
                         const int m = min(n, N - 1);
-                        const double nlo = tau_nb(1 + 2 * a, m), nc = tau_nb(0, m);
-                        const double nhi = tau_nb(2 + 2 * a, m);
+                        const double ilo = 1.0 / tau_nb(1 + 2 * a, m);
+                        const double ihi = 1.0 / tau_nb(2 + 2 * a, m);
                         double fL, fR;
-                        tau_face(s_ftau[wave][2 * a], nlo, nc, fL, fR);
+                        tau_face_inv(s_ftau[wave][2 * a], ilo, tinc[ch], fL, fR);
                         ulo *= Real((f & lp) ? fL : fR);
-                        tau_face(s_ftau[wave][2 * a + 1], nc, nhi, fL, fR);
+                        tau_face_inv(s_ftau[wave][2 * a + 1], tinc[ch], ihi, fL, fR);
                         uhi *= Real((f & hp) ? fL : fR);
                     }
                     const Real Flo = (a ? cyl[ch] : cxl[ch]) * ulo;
@@ -679,7 +685,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     if constexpr (TAU) {
                         const int m = min(n, N - 1);
                         double fL, fR;
-                        tau_face(s_ftau[wave][5], tau_nb(0, m), tau_nb(6, m), fL, fR);
+                        tau_face_inv(s_ftau[wave][5], tinc[ch], 1.0 / tau_nb(6, m), fL, fR);
                         uhi *= Real((f & kSzP) ? fL : fR);
                     }
                     (void)ulo;
