@@ -165,10 +165,10 @@ def _upload_initial(prob, dtype, dev):
 
 
 def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag, integrator=1,
-                    ang_recon=0, rad_velocity=0, cond_T=False):
+                    ang_recon=0, rad_velocity=0, cond_T=False, tau_coeff=0.0):
     full = W.make_problem(cfg)
     full.integrator = integrator
-    full.ang_recon, full.rad_velocity = ang_recon, rad_velocity
+    full.ang_recon, full.rad_velocity, full.tau_coeff = ang_recon, rad_velocity, tau_coeff
     dt = O.max_dt(O.setup(full), full.cfl)
     dev = torch.device("cuda", 0)
     g = rt.Grid(full, precision)
@@ -185,7 +185,7 @@ def _full_vs_subbox(cfg, precision, steps, origin, m, tol_I, tol_T, tag, integra
     halo = 2 * steps * integrator          # PLM reach: two cells per stage
     sub = W.make_problem(cfg, sub=(tuple(o - halo for o in origin), tuple(m + 2 * halo for _ in range(3))))
     sub.integrator = integrator
-    sub.ang_recon, sub.rad_velocity = ang_recon, rad_velocity
+    sub.ang_recon, sub.rad_velocity, sub.tau_coeff = ang_recon, rad_velocity, tau_coeff
     Io, To, _, _, _ = oracle_run(sub, steps, dt)
     N = full.n
     ii = [(origin[a] + np.arange(m)) % N[a] for a in range(3)]
@@ -252,6 +252,16 @@ def test_c5_full_size_fp64_subbox():
     # kernel by 1.8e-12; T by 8e-16)
     _full_vs_subbox("c5", rt.RT_F64, 2, (150, 58, 10), 12, 1e-11, F64_T,
                     "c5 full 256x128x256x362 fp64 2 steps, torus block 12^3")
+
+
+@pytest.mark.parametrize("prec", [rt.RT_F64, rt.RT_F32])
+def test_c2_full_size_two_stage_tau_subbox(prec):
+    # the production options, two stages with the optical-depth-aware flux
+    # (C_tau = 5), on the column kernel at the benchmark's 128^3 x 162 size
+    tol = (F64_I, F64_T) if prec == rt.RT_F64 else (F32_I, F32_T)
+    _full_vs_subbox("c2", prec, 2, (-4, 56, 56), 12, *tol,
+                    "c2 full 128^3 two-stage tau %s 2 steps, block 12^3"
+                    % ("fp64" if prec == rt.RT_F64 else "fp32"), integrator=2, tau_coeff=5.0)
 
 
 def test_c3_full_size_mapr_subbox_fp64():
