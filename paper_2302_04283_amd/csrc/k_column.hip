@@ -613,7 +613,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
             if constexpr (TAU) {
                 tau_plane(tfl);
 #pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) tinc[ch] = 1.0 / tau_nb(0, min(lbase + kWave * ch, N - 1));
+                for (int ch = 0; ch < NCH; ++ch) tinc[ch] = rcp64(tau_nb(0, min(lbase + kWave * ch, N - 1)));
             }
             const bool lum_here = lum_col || (G.lum_axis == 2 && z == (G.lum_side ? G.n2 - 1 : 0));
             // ------------------------------------------------------ transport
@@ -654,8 +654,8 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     axis_faces2(v, plm, f & lp, f & hp, ulo, uhi);
                     if constexpr (TAU) {
                         const int m = min(n, N - 1);
-                        const double ilo = 1.0 / tau_nb(1 + 2 * a, m);
-                        const double ihi = 1.0 / tau_nb(2 + 2 * a, m);
+                        const double ilo = rcp64(tau_nb(1 + 2 * a, m));
+                        const double ihi = rcp64(tau_nb(2 + 2 * a, m));
                         double fL, fR;
                         tau_face_inv(s_ftau[wave][2 * a], ilo, tinc[ch], fL, fR);
                         ulo *= Real((f & lp) ? fL : fR);
@@ -685,7 +685,7 @@ __global__ __launch_bounds__(kColBlock) __attribute__((amdgpu_waves_per_eu(col_w
                     if constexpr (TAU) {
                         const int m = min(n, N - 1);
                         double fL, fR;
-                        tau_face_inv(s_ftau[wave][5], tinc[ch], 1.0 / tau_nb(6, m), fL, fR);
+                        tau_face_inv(s_ftau[wave][5], tinc[ch], rcp64(tau_nb(6, m)), fL, fR);
                         uhi *= Real((f & kSzP) ? fL : fR);
                     }
                     (void)ulo;

@@ -194,7 +194,8 @@ __device__ __forceinline__ void axis_fluid(const DevGrid &G, const Cell &x, int 
 
 // Flux factors (1 + (g - g_L), 1 + (g - g_R)) of a face with interpolating
 // factor f between cells with fluid-frame n^0bar nL and nR (tau_face_inv:
-// from 1/nL and 1/nR, formed once per cell where a cell borders two faces).
+// from 1/nL and 1/nR, formed once per cell where a cell borders two faces,
+// by the refined hardware reciprocal in every kernel).
 __device__ __forceinline__ void tau_face_inv(double f, double inL, double inR, double &facL,
                                              double &facR) {
     const double gL = -f * (1.0 + inL), gR = -f * (1.0 + inR);
@@ -203,7 +204,7 @@ __device__ __forceinline__ void tau_face_inv(double f, double inL, double inR, d
     facR = 1.0 + (g - gR);
 }
 __device__ __forceinline__ void tau_face(double f, double nL, double nR, double &facL, double &facR) {
-    tau_face_inv(f, 1.0 / nL, 1.0 / nR, facL, facR);
+    tau_face_inv(f, rcp64(nL), rcp64(nR), facL, facR);
 }
 
 template <typename Real>
